@@ -1,0 +1,214 @@
+/*
+ * sof.h -- C ABI of the MI355X (gfx950) Sorted Opacity Fields hot path.
+ *
+ * The library computes, for 3D Gaussians (mean mu, scale s, rotation quaternion q,
+ * opacity o, spherical-harmonic colour f; Sec. 3.1 of the SOF paper):
+ *
+ *   sof_project        per (camera, Gaussian) preprocessing: culling, the per-ray
+ *                      quadric constants of the ray-Gaussian evaluation (Sec. 3.1,
+ *                      Eq. (7)-(10); App. A.1), the opacity-aware bound E = sqrt(2 ln 255 o)
+ *                      (Eq. (3)), SH colour, normal, screen rectangle, depth keys.
+ *   sof_bin_sort       duplication of every Gaussian into the screen tiles it touches and
+ *                      the per-tile key sort (level 0 of the hierarchical resort; Sec. 3.1).
+ *   sof_render_fwd     per-pixel hierarchical resort by the ray depth of maximum response
+ *                      (Eq. (2)/(9)) with a bounded window, front-to-back alpha blending
+ *                      (Eq. (1)) of colour, normal and opacity, and the exact 0.5-level-set
+ *                      depth (Sec. 3.2 "Exact Depth", App. A.3).
+ *   sof_render_bwd     adjoint of render + project: replays each pixel's order front to back,
+ *                      recomputing transmittance, and writes gradients for mu, s, q, o, f.
+ *   sof_opacity_query  opacity field O(x) = min over views of O_N(x) (Eq. (12)-(13)) at
+ *                      arbitrary points, with tile scheduling of points (Sec. 3.4, Eq. (14))
+ *                      and z_min early stopping (Eq. (15)); all views in one persistent launch.
+ *
+ * Conventions shared by every entry point
+ *   - All array arguments are DEVICE pointers unless named h_*, row-major, contiguous,
+ *     float32 unless stated.  The caller owns every buffer; the library never allocates,
+ *     frees or synchronises.  Work is enqueued on `stream` in order; no entry point reads
+ *     a device value back to the host, so a sequence of calls can be captured in a graph.
+ *   - Cameras are passed twice: h_cams (host copy, used for launch sizes) and d_cams
+ *     (identical device copy, read by kernels).  World -> camera is x_c = R x + t with
+ *     OpenCV axes (x right, y down, z forward); pixel (px, py) has its centre at
+ *     (px + 1/2, py + 1/2); intrinsics fx, fy, cx, cy in pixels.
+ *   - Images of several cameras are concatenated in camera order.  Per camera, a C-channel
+ *     image is planar [C, H, W]; camera c's block starts at C * sum_{c'<c} W_c' H_c'.
+ *   - Return value: SOF_OK (0) or a negative sof_status.  Argument checks happen before
+ *     anything is enqueued.  A device-side condition (instance capacity exceeded) cannot be
+ *     returned from an asynchronous call; it is recorded in the status word inside the
+ *     `bins` buffer (see sof_read_status_offset) and the affected work is clipped so that
+ *     nothing is written out of bounds.
+ *   - Thread safety: no global mutable state; calls on different streams with different
+ *     buffers may run concurrently.
+ */
+#ifndef SOF_H
+#define SOF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum sof_status {
+  SOF_OK = 0,
+  SOF_E_ARG = -1,          /* null pointer, negative size, sh_degree > 3, bad tile/window   */
+  SOF_E_WORKSPACE = -2,    /* a workspace buffer is smaller than sof_workspace_size asks   */
+  SOF_E_CAPACITY = -3,     /* (device status bit) more tile instances than `capacity`       */
+  SOF_E_HIP = -4,          /* a HIP launch failed (hipGetLastError after enqueue)          */
+  SOF_E_UNSUPPORTED = -5   /* window or tile size without a compiled kernel               */
+} sof_status;
+
+/* Option flags */
+enum {
+  SOF_DEPTH_MEDIAN = 1u << 0,    /* depth output = t*_k of the crossing Gaussian (GOF median
+                                    depth) instead of the exact 0.5-level-set depth           */
+  SOF_DEPTH_GRAD_FULL = 1u << 1, /* render_bwd: differentiate the exact-depth correction
+                                    (App. A.3) too; default treats it as a constant, as the
+                                    paper does, so d depth = d t*_k                           */
+  SOF_QUERY_KEYS = 1u << 2       /* set internally by sof_opacity_query: tile lists sorted by
+                                    z_min (Eq. (15)) instead of the mean's view depth          */
+};
+
+/* Gaussians, Sec. 3.1: n primitives, activated parameters. */
+typedef struct sof_gaussians {
+  int64_t n;                 /* number of Gaussians, 0 <= n < 2^31                            */
+  int32_t sh_degree;         /* 0..3; K = (sh_degree + 1)^2 coefficients per channel          */
+  int32_t reserved;
+  const float* means;        /* [n,3] world-space centres                                      */
+  const float* scales;       /* [n,3] standard deviations along the rotated axes (> 0)         */
+  const float* quats;        /* [n,4] rotation quaternion (w,x,y,z); normalised internally     */
+  const float* opacities;    /* [n]   in [0,1]                                                  */
+  const float* sh;           /* [n,K,3] real SH coefficients, coefficient l^2 + l + m          */
+} sof_gaussians;
+
+/* Pinhole camera (72 bytes). */
+typedef struct sof_camera {
+  float R[9];                /* world -> camera rotation, row-major                            */
+  float t[3];                /* world -> camera translation                                    */
+  float fx, fy, cx, cy;      /* intrinsics in pixels                                           */
+  int32_t width, height;     /* image size in pixels (>= 1)                                    */
+} sof_camera;
+
+typedef struct sof_options {
+  int32_t tile;              /* screen tile side: 8, 16 or 32                                  */
+  int32_t window;            /* per-pixel resort window W: 0 (no resort), 1, 2, 4, 8, 16, 32 */
+  float near_plane;          /* tau_n; the paper's near plane is 0.2                           */
+  float bg[3];               /* background colour added with weight T_end (default 0)          */
+  uint32_t flags;            /* SOF_* flags                                                    */
+  int32_t reserved;
+  int64_t capacity;          /* maximum number of tile instances (all cameras), < 2^31         */
+} sof_options;
+
+/*
+ * Sizes of the three caller-owned device buffers for a render of n Gaussians over the
+ * given cameras:
+ *   proj   per (camera, Gaussian) records written by sof_project          ~ 160 B x cams x n
+ *   bins   tile instances, sort buffers, tile ranges, status word          ~ 24 B x capacity
+ *   grads  per-instance gradient partials used only by sof_render_bwd      64 B x capacity
+ * Any output pointer may be NULL.  Returns SOF_E_ARG on invalid arguments.
+ */
+int sof_workspace_size(int64_t n, const sof_camera* h_cams, int32_t n_cams, const sof_options* opts,
+                       size_t* proj_bytes, size_t* bins_bytes, size_t* grad_bytes);
+
+/* Byte offset, inside `bins`, of the device status block:
+ *   int64 [0] instance count K requested by the last sof_bin_sort (may exceed capacity)
+ *   int32 [2] status bits: 1 = capacity exceeded (K > capacity; lists were clipped)       */
+size_t sof_read_status_offset(void);
+
+/*
+ * sof_project -- Sec. 3.1 (Eq. (3), (7)-(10)), App. A.1.
+ * For every camera c and Gaussian i writes into `proj` the record the rasteriser needs:
+ * liveness (o >= 1/255 and view z of the mean > near_plane), the quadric constants of the
+ * pixel-ray evaluation (computed in float64, stored in float32 in a cancellation-free form
+ * relative to the projected centre), opacity, colour max(0, SH(dir) + 1/2) with dir from
+ * the camera centre to the mean, the normal (shortest axis, facing the camera), the
+ * inclusive pixel rectangle covering the E-ellipsoid and the depth keys.  Overwrites proj.
+ */
+int sof_project(const sof_gaussians* g, const sof_camera* h_cams, const sof_camera* d_cams,
+                int32_t n_cams, const sof_options* opts, void* proj, size_t proj_bytes,
+                hipStream_t stream);
+
+/*
+ * sof_bin_sort -- the per-tile key sort (level 0 of the hierarchical resort, Sec. 3.1).
+ * Emits one instance per (camera, Gaussian, touched tile), sorts instances by
+ * (global tile, float32 view depth of the mean, Gaussian index) with a stable LSD radix
+ * sort and writes per-tile [start, end) ranges.  With SOF_QUERY_KEYS the depth key is
+ * z_min = mu_z - E sqrt(Sigma_zz) instead (Eq. (15)).  Reads proj, overwrites bins.
+ * Instances beyond opts->capacity are dropped and status bit 1 is set.
+ */
+int sof_bin_sort(int64_t n, const sof_camera* h_cams, const sof_camera* d_cams, int32_t n_cams,
+                 const sof_options* opts, const void* proj, size_t proj_bytes, void* bins,
+                 size_t bins_bytes, hipStream_t stream);
+
+/*
+ * sof_render_fwd -- Eq. (1), (2), Sec. 3.2.
+ * For every pixel: walks its tile's list, keeps Gaussians with alpha = min(0.99, o G*) >=
+ * 1/255 whose peak lies beyond the near plane, re-sorts them by the ray distance t* of
+ * maximum response with a window of opts->window entries, and blends front to back,
+ * stopping before a Gaussian that would drop T below 1e-4.  Outputs (any may be NULL):
+ *   rgb    [3,H,W] per camera   sum w c + bg T_end
+ *   acc    [H,W]                1 - T_end
+ *   depth  [H,W]                exact depth t_k - sqrt(2 ln(G*_k / g) / A_k) on the ray,
+ *                               g = (T_k - 1/2) / (T_k o_k), k = first Gaussian with
+ *                               T_k > 1/2 >= T_k (1 - alpha_k); 0 without a crossing
+ *                               (t*_k with SOF_DEPTH_MEDIAN)
+ *   normal [3,H,W]              sum w n (not normalised)
+ *   aux    [4,H,W] float32 bits T_end, n_emitted (int32), k (int32 Gaussian index or -1),
+ *                               T_k -- needed by sof_render_bwd.
+ */
+int sof_render_fwd(int64_t n, const sof_camera* h_cams, const sof_camera* d_cams, int32_t n_cams,
+                   const sof_options* opts, const void* proj, size_t proj_bytes, const void* bins,
+                   size_t bins_bytes, float* rgb, float* acc, float* depth, float* normal, float* aux,
+                   hipStream_t stream);
+
+/*
+ * sof_render_bwd -- adjoint of sof_render_fwd and sof_project.
+ * Inputs: the same g, cameras, options, proj and bins as the forward call, its rgb,
+ * normal and aux outputs, and upstream gradients d_rgb, d_acc, d_depth, d_normal (NULL =
+ * zero).  Each pixel's forward order is replayed front to back; suffix sums come from the
+ * stored totals.  Writes (overwrites) d_means [n,3], d_scales [n,3], d_quats [n,4],
+ * d_opacities [n], d_sh [n,K,3].  `grads` is scratch.  Deterministic: per-instance partials
+ * are reduced in a fixed order.
+ */
+int sof_render_bwd(const sof_gaussians* g, const sof_camera* h_cams, const sof_camera* d_cams,
+                   int32_t n_cams, const sof_options* opts, const void* proj, size_t proj_bytes,
+                   const void* bins, size_t bins_bytes, const float* rgb, const float* normal,
+                   const float* aux, const float* d_rgb, const float* d_acc, const float* d_depth,
+                   const float* d_normal, void* grads, size_t grad_bytes, float* d_means,
+                   float* d_scales, float* d_quats, float* d_opacities, float* d_sh,
+                   hipStream_t stream);
+
+/*
+ * Workspace for sof_opacity_query: like sof_workspace_size with the per-view tile lists
+ * sorted by z_min plus the (view, point) schedule.  `pv_capacity` bounds the number of
+ * (point, view) pairs that project inside a view (<= n_points * n_cams).
+ */
+int sof_query_workspace_size(int64_t n, const sof_camera* h_cams, int32_t n_cams,
+                             const sof_options* opts, int64_t n_points, int64_t pv_capacity,
+                             size_t* proj_bytes, size_t* bins_bytes, size_t* sched_bytes);
+
+/*
+ * sof_opacity_query -- Eq. (12)-(13), App. A.2, Sec. 3.4.
+ * opacity[p] = min over cameras v that see points[p] (view z > near_plane and projection
+ * inside the image) of O_N = 1 - prod_i (1 - alpha_i), alpha_i = min(0.99, o_i G_i(t_eval)),
+ * t_eval = min(t*_i, |x - c_v|), counting Gaussians with alpha_i >= 1/255 whose evaluated
+ * point lies beyond the near plane; 1 where no camera sees the point.  Points are scheduled
+ * per (view, tile) in blocks of 256 sorted by depth (Eq. (14)); each tile's Gaussians are
+ * sorted by z_min and the walk stops at z_min > z(x) (Eq. (15)) or once the partial O_N
+ * already reaches the point's running minimum.  All (view, tile, block) work items run in
+ * one persistent launch.  Overwrites opacity [n_points].
+ */
+int sof_opacity_query(const sof_gaussians* g, const sof_camera* h_cams, const sof_camera* d_cams,
+                      int32_t n_cams, const sof_options* opts, const float* points, int64_t n_points,
+                      int64_t pv_capacity, float* opacity, void* proj, size_t proj_bytes, void* bins,
+                      size_t bins_bytes, void* sched, size_t sched_bytes, hipStream_t stream);
+
+/* Human-readable text for a sof_status value (static storage). */
+const char* sof_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SOF_H */

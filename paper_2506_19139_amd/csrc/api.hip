@@ -1,0 +1,207 @@
+// C ABI entry points: argument checks, buffer layouts and kernel launches.  No allocation,
+// no synchronisation, no device-to-host reads.
+#include <stdlib.h>
+#include <string.h>
+#include <stdio.h>
+
+#include "launch.h"
+
+using namespace sof;
+
+namespace {
+
+bool trace_enabled() {
+  static const int on = [] {
+    const char* e = getenv("SOF_TRACE");
+    return (e && e[0] == '1') ? 1 : 0;
+  }();
+  return on != 0;
+}
+
+int check_opts(const sof_options* o) {
+  if (!o) return SOF_E_ARG;
+  if (o->tile != 8 && o->tile != 16 && o->tile != 32) return SOF_E_ARG;
+  if (o->window < 0) return SOF_E_ARG;
+  if (!render_supported(o->tile, o->window)) return SOF_E_UNSUPPORTED;
+  if (!(o->near_plane > 0.f)) return SOF_E_ARG;
+  if (o->capacity < 0 || o->capacity >= (int64_t(1) << 31)) return SOF_E_ARG;
+  return SOF_OK;
+}
+
+int check_cams(const sof_camera* h, int n_cams, int64_t* n_tiles, int tile) {
+  if (!h || n_cams < 1) return SOF_E_ARG;
+  int64_t t = 0;
+  for (int c = 0; c < n_cams; ++c) {
+    if (h[c].width < 1 || h[c].height < 1 || h[c].width > 32767 || h[c].height > 32767) return SOF_E_ARG;
+    if (!(h[c].fx > 0.f) || !(h[c].fy > 0.f)) return SOF_E_ARG;
+    t += (int64_t)((h[c].width + tile - 1) / tile) * ((h[c].height + tile - 1) / tile);
+  }
+  if (t >= (int64_t(1) << 31)) return SOF_E_ARG;
+  *n_tiles = t;
+  return SOF_OK;
+}
+
+int check_gauss(const sof_gaussians* g, bool need_params) {
+  if (!g || g->n < 0 || g->n >= (int64_t(1) << 31)) return SOF_E_ARG;
+  if (g->sh_degree < 0 || g->sh_degree > 3) return SOF_E_ARG;
+  if (need_params && g->n > 0 && (!g->means || !g->scales || !g->quats || !g->opacities || !g->sh)) return SOF_E_ARG;
+  return SOF_OK;
+}
+
+int hip_status(hipError_t e) { return e == hipSuccess ? SOF_OK : SOF_E_HIP; }
+
+int sorted_parity(int64_t n_tiles) { return (((32 + bits_for(n_tiles)) + 7) / 8) & 1; }
+
+}  // namespace
+
+extern "C" {
+
+size_t sof_read_status_offset(void) { return 0; }
+
+const char* sof_strerror(int code) {
+  switch (code) {
+    case SOF_OK: return "ok";
+    case SOF_E_ARG: return "invalid argument";
+    case SOF_E_WORKSPACE: return "workspace buffer too small";
+    case SOF_E_CAPACITY: return "tile-instance capacity exceeded";
+    case SOF_E_HIP: return "HIP launch failed";
+    case SOF_E_UNSUPPORTED: return "unsupported tile/window combination";
+    default: return "unknown sof status";
+  }
+}
+
+int sof_workspace_size(int64_t n, const sof_camera* h_cams, int32_t n_cams, const sof_options* opts,
+                       size_t* proj_bytes, size_t* bins_bytes, size_t* grad_bytes) {
+  int st = check_opts(opts);
+  if (st) return st;
+  if (n < 0 || n >= (int64_t(1) << 31)) return SOF_E_ARG;
+  int64_t n_tiles = 0;
+  if ((st = check_cams(h_cams, n_cams, &n_tiles, opts->tile))) return st;
+  const int64_t vn = n * n_cams;
+  if (proj_bytes) *proj_bytes = ProjLayout::make(vn).total;
+  if (bins_bytes) *bins_bytes = BinsLayout::make(vn, n_cams, opts->capacity, n_tiles).total;
+  if (grad_bytes) *grad_bytes = (size_t)opts->capacity * kGradFields * sizeof(float);
+  return SOF_OK;
+}
+
+int sof_project(const sof_gaussians* g, const sof_camera* h_cams, const sof_camera* d_cams, int32_t n_cams,
+                const sof_options* opts, void* proj, size_t proj_bytes, hipStream_t stream) {
+  int st = check_opts(opts);
+  if (st) return st;
+  if ((st = check_gauss(g, true))) return st;
+  int64_t n_tiles = 0;
+  if ((st = check_cams(h_cams, n_cams, &n_tiles, opts->tile))) return st;
+  if (!d_cams || (!proj && g->n > 0)) return SOF_E_ARG;
+  if (proj_bytes < ProjLayout::make(g->n * n_cams).total) return SOF_E_WORKSPACE;
+  if (trace_enabled()) fprintf(stderr, "[sof] project n=%lld cams=%d\n", (long long)g->n, n_cams);
+  return hip_status(launch_project(g, d_cams, n_cams, opts->near_plane, proj, stream));
+}
+
+int sof_bin_sort(int64_t n, const sof_camera* h_cams, const sof_camera* d_cams, int32_t n_cams,
+                 const sof_options* opts, const void* proj, size_t proj_bytes, void* bins, size_t bins_bytes,
+                 hipStream_t stream) {
+  int st = check_opts(opts);
+  if (st) return st;
+  if (n < 0 || n >= (int64_t(1) << 31)) return SOF_E_ARG;
+  int64_t n_tiles = 0;
+  if ((st = check_cams(h_cams, n_cams, &n_tiles, opts->tile))) return st;
+  if (!d_cams || !bins || (!proj && n > 0)) return SOF_E_ARG;
+  const int64_t vn = n * n_cams;
+  if (proj_bytes < ProjLayout::make(vn).total) return SOF_E_WORKSPACE;
+  if (bins_bytes < BinsLayout::make(vn, n_cams, opts->capacity, n_tiles).total) return SOF_E_WORKSPACE;
+  if (trace_enabled())
+    fprintf(stderr, "[sof] bin_sort n=%lld cams=%d tiles=%lld cap=%lld\n", (long long)n, n_cams, (long long)n_tiles,
+            (long long)opts->capacity);
+  int parity = 0;
+  return hip_status(launch_bin_sort(n, d_cams, n_cams, n_tiles, opts->tile, opts->capacity,
+                                    (opts->flags & SOF_QUERY_KEYS) ? 1 : 0, proj, bins, stream, &parity));
+}
+
+static int fill_fwd_args(int64_t n, const sof_camera* h_cams, const sof_camera* d_cams, int32_t n_cams,
+                         const sof_options* opts, const void* proj, size_t proj_bytes, const void* bins,
+                         size_t bins_bytes, RenderFwdArgs* a, int64_t* n_tiles_out) {
+  int st = check_opts(opts);
+  if (st) return st;
+  if (n < 0 || n >= (int64_t(1) << 31)) return SOF_E_ARG;
+  int64_t n_tiles = 0;
+  if ((st = check_cams(h_cams, n_cams, &n_tiles, opts->tile))) return st;
+  if (!d_cams || !bins || (!proj && n > 0)) return SOF_E_ARG;
+  const int64_t vn = n * n_cams;
+  const ProjLayout P = ProjLayout::make(vn);
+  const BinsLayout B = BinsLayout::make(vn, n_cams, opts->capacity, n_tiles);
+  if (proj_bytes < P.total) return SOF_E_WORKSPACE;
+  if (bins_bytes < B.total) return SOF_E_WORKSPACE;
+  const char* pb = (const char*)proj;
+  const char* bb = (const char*)bins;
+  memset(a, 0, sizeof(*a));
+  a->n = n;
+  a->cams = d_cams;
+  a->cam_info = (const CamInfo*)(bb + B.cams);
+  a->n_cams = n_cams;
+  a->near_plane = opts->near_plane;
+  a->bg[0] = opts->bg[0]; a->bg[1] = opts->bg[1]; a->bg[2] = opts->bg[2];
+  a->flags = opts->flags;
+  a->geom = (const float4*)(pb + P.geom);
+  a->app = (const float4*)(pb + P.app);
+  a->ranges = (const int2*)(bb + B.ranges);
+  a->vals = (const uint32_t*)(bb + (sorted_parity(n_tiles) ? B.vals1 : B.vals0));
+  a->gid = (const int32_t*)(bb + B.gid);
+  *n_tiles_out = n_tiles;
+  return SOF_OK;
+}
+
+int sof_render_fwd(int64_t n, const sof_camera* h_cams, const sof_camera* d_cams, int32_t n_cams,
+                   const sof_options* opts, const void* proj, size_t proj_bytes, const void* bins, size_t bins_bytes,
+                   float* rgb, float* acc, float* depth, float* normal, float* aux, hipStream_t stream) {
+  RenderFwdArgs a;
+  int64_t n_tiles = 0;
+  int st = fill_fwd_args(n, h_cams, d_cams, n_cams, opts, proj, proj_bytes, bins, bins_bytes, &a, &n_tiles);
+  if (st) return st;
+  a.rgb = rgb; a.acc = acc; a.depth = depth; a.normal = normal; a.aux = aux;
+  if (trace_enabled())
+    fprintf(stderr, "[sof] render_fwd tiles=%lld tile=%d window=%d\n", (long long)n_tiles, opts->tile, opts->window);
+  return hip_status(launch_render_fwd(a, opts->tile, opts->window, n_tiles, stream));
+}
+
+int sof_render_bwd(const sof_gaussians* g, const sof_camera* h_cams, const sof_camera* d_cams, int32_t n_cams,
+                   const sof_options* opts, const void* proj, size_t proj_bytes, const void* bins, size_t bins_bytes,
+                   const float* rgb, const float* normal, const float* aux, const float* d_rgb, const float* d_acc,
+                   const float* d_depth, const float* d_normal, void* grads, size_t grad_bytes, float* d_means,
+                   float* d_scales, float* d_quats, float* d_opacities, float* d_sh, hipStream_t stream) {
+  int st = check_gauss(g, true);
+  if (st) return st;
+  RenderBwdArgs b;
+  int64_t n_tiles = 0;
+  st = fill_fwd_args(g->n, h_cams, d_cams, n_cams, opts, proj, proj_bytes, bins, bins_bytes, &b.f, &n_tiles);
+  if (st) return st;
+  if (!rgb || !aux) return SOF_E_ARG;
+  if (g->n > 0 && (!d_means || !d_scales || !d_quats || !d_opacities || !d_sh)) return SOF_E_ARG;
+  if (!grads && opts->capacity > 0) return SOF_E_ARG;
+  if (grad_bytes < (size_t)opts->capacity * kGradFields * sizeof(float)) return SOF_E_WORKSPACE;
+  const int64_t vn = g->n * n_cams;
+  const ProjLayout P = ProjLayout::make(vn);
+  const BinsLayout B = BinsLayout::make(vn, n_cams, opts->capacity, n_tiles);
+  const char* pb = (const char*)proj;
+  const char* bb = (const char*)bins;
+  b.bwdr = (const float4*)(pb + P.bwdr);
+  b.out_rgb = rgb; b.out_normal = normal;
+  b.d_rgb = d_rgb; b.d_acc = d_acc; b.d_depth = d_depth; b.d_normal = d_normal;
+  b.grads = (float*)grads;
+  b.f.aux = (float*)aux;
+  if (trace_enabled())
+    fprintf(stderr, "[sof] render_bwd tiles=%lld tile=%d window=%d\n", (long long)n_tiles, opts->tile, opts->window);
+  hipError_t e = launch_render_bwd(b, opts->tile, opts->window, n_tiles, stream);
+  if (e != hipSuccess) return SOF_E_HIP;
+  ProjectBwdArgs pa;
+  pa.means = g->means; pa.scales = g->scales; pa.quats = g->quats; pa.opac = g->opacities; pa.sh = g->sh;
+  pa.sh_degree = g->sh_degree; pa.n = g->n; pa.cams = d_cams; pa.n_cams = n_cams;
+  pa.counts = (const int32_t*)(bb + B.counts);
+  pa.offsets = (const int64_t*)(bb + B.offsets);
+  pa.count_total = (const int64_t*)(bb + B.status);
+  pa.cap = opts->capacity;
+  pa.grads = (const float*)grads;
+  pa.d_means = d_means; pa.d_scales = d_scales; pa.d_quats = d_quats; pa.d_opac = d_opacities; pa.d_sh = d_sh;
+  return hip_status(launch_project_bwd(pa, stream));
+}
+
+}  // extern "C"

@@ -1,0 +1,338 @@
+// Duplication of Gaussians into tiles and the per-tile key sort (level 0 of the
+// hierarchical resort, Sec. 3.1), plus the device-wide scan and the stable LSD radix sort
+// it is built from.  Instance counts stay on the device: every grid is sized from static
+// capacities and reads the live count from the status block, so the sequence can be
+// captured in a graph.
+//
+// Radix sort: 8-bit digits, 2048 keys per workgroup of 256 lanes (4 wave64s).  Per pass a
+// histogram kernel writes per-(digit, block) counts digit-major, an exclusive scan turns
+// them into global offsets, and a scatter kernel ranks keys stably inside the workgroup:
+// each wave owns 512 consecutive keys, walks them in input order, groups equal digits with
+// 8 ballots and keeps running per-digit counts in LDS.
+#include "launch.h"
+
+namespace sof {
+
+// ------------------------------------------------------------------------- scan
+
+template <typename Tin, typename Tacc>
+__device__ inline Tacc block_exclusive_scan(Tacc v, Tacc* lds_wave, Tacc& total) {
+  // 256 threads = 4 waves of 64
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  Tacc x = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    Tacc y = __shfl_up(x, d, 64);
+    if (lane >= d) x += y;
+  }
+  if (lane == 63) lds_wave[w] = x;
+  __syncthreads();
+  Tacc base = 0;
+  total = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    Tacc t = lds_wave[k];
+    if (k < w) base += t;
+    total += t;
+  }
+  __syncthreads();
+  return base + x - v;
+}
+
+template <typename Tin, typename Tacc>
+__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const Tin* in, int64_t n, Tacc* sums) {
+  __shared__ Tacc lw[4];
+  const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanItems;
+  Tacc s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k)
+    if (base + k < n) s += (Tacc)in[base + k];
+  Tacc total;
+  block_exclusive_scan<Tin, Tacc>(s, lw, total);
+  if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+// Exclusive scan of the chunk sums in one workgroup; writes the grand total.
+template <typename Tacc>
+__global__ __launch_bounds__(kScanThreads) void k_scan_chunks(Tacc* sums, int64_t nchunks, int64_t* total_out) {
+  __shared__ Tacc lw[4];
+  Tacc carry = 0;
+  for (int64_t b = 0; b < nchunks; b += kScanThreads) {
+    const int64_t i = b + threadIdx.x;
+    Tacc v = i < nchunks ? sums[i] : 0;
+    Tacc tot;
+    Tacc ex = block_exclusive_scan<Tacc, Tacc>(v, lw, tot);
+    if (i < nchunks) sums[i] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0 && total_out) *total_out = (int64_t)carry;
+}
+
+template <typename Tin, typename Tout>
+__global__ __launch_bounds__(kScanThreads) void k_scan_apply(const Tin* in, int64_t n, const Tout* sums, Tout* out) {
+  __shared__ Tout lw[4];
+  const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanItems;
+  Tout v[kScanItems];
+  Tout s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    v[k] = base + k < n ? (Tout)in[base + k] : 0;
+    s += v[k];
+  }
+  Tout total;
+  Tout run = sums[blockIdx.x] + block_exclusive_scan<Tout, Tout>(s, lw, total);
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    if (base + k < n) out[base + k] = run;
+    run += v[k];
+  }
+}
+
+template <typename Tin, typename Tout>
+hipError_t exclusive_scan(const Tin* in, int64_t n, Tout* out, Tout* tmp, int64_t* total, hipStream_t s) {
+  if (n <= 0) {
+    if (total) hipLaunchKernelGGL((k_scan_chunks<Tout>), dim3(1), dim3(kScanThreads), 0, s, tmp, (int64_t)0, total);
+    return hipGetLastError();
+  }
+  const int64_t nch = div_up(n, kScanChunk);
+  hipLaunchKernelGGL((k_scan_reduce<Tin, Tout>), dim3((unsigned)nch), dim3(kScanThreads), 0, s, in, n, tmp);
+  hipLaunchKernelGGL((k_scan_chunks<Tout>), dim3(1), dim3(kScanThreads), 0, s, tmp, nch, total);
+  hipLaunchKernelGGL((k_scan_apply<Tin, Tout>), dim3((unsigned)nch), dim3(kScanThreads), 0, s, in, n, tmp, out);
+  return hipGetLastError();
+}
+
+template hipError_t exclusive_scan<int32_t, int64_t>(const int32_t*, int64_t, int64_t*, int64_t*, int64_t*, hipStream_t);
+template hipError_t exclusive_scan<int32_t, int32_t>(const int32_t*, int64_t, int32_t*, int32_t*, int64_t*, hipStream_t);
+
+// ------------------------------------------------------------------------- radix sort
+
+__device__ inline int64_t live_count(const int64_t* count, int64_t cap) {
+  const int64_t k = *count;
+  return k < cap ? k : cap;
+}
+
+template <typename K>
+__global__ __launch_bounds__(kSortThreads) void k_radix_hist(const K* keys, const int64_t* count, int64_t cap,
+                                                             int shift, int32_t* hist, int64_t nblocks) {
+  __shared__ int32_t cnt[4][256];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int t = threadIdx.x; t < 4 * 256; t += kSortThreads) (&cnt[0][0])[t] = 0;
+  __syncthreads();
+  const int64_t n = live_count(count, cap);
+  const int64_t start = (int64_t)blockIdx.x * kSortTile + (int64_t)w * (kSortItems * 64);
+#pragma unroll
+  for (int it = 0; it < kSortItems; ++it) {
+    const int64_t idx = start + it * 64 + lane;
+    if (idx < n) {
+      const int d = (int)((keys[idx] >> shift) & 0xFF);
+      atomicAdd(&cnt[w][d], 1);
+    }
+  }
+  __syncthreads();
+  const int t = threadIdx.x;
+  hist[(int64_t)t * nblocks + blockIdx.x] = cnt[0][t] + cnt[1][t] + cnt[2][t] + cnt[3][t];
+}
+
+template <typename K>
+__global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const K* keys_in, const uint32_t* vals_in, K* keys_out,
+                                                                uint32_t* vals_out, const int64_t* count, int64_t cap,
+                                                                int shift, const int32_t* hist, int64_t nblocks) {
+  __shared__ int32_t wc[4][256];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int t = threadIdx.x; t < 4 * 256; t += kSortThreads) (&wc[0][0])[t] = 0;
+  __syncthreads();
+  const int64_t n = live_count(count, cap);
+  const int64_t start = (int64_t)blockIdx.x * kSortTile + (int64_t)w * (kSortItems * 64);
+  K key[kSortItems];
+  uint32_t val[kSortItems];
+  int rank[kSortItems];
+  const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+#pragma unroll
+  for (int it = 0; it < kSortItems; ++it) {
+    const int64_t idx = start + it * 64 + lane;
+    const bool valid = idx < n;
+    key[it] = valid ? keys_in[idx] : K(0);
+    val[it] = valid ? vals_in[idx] : 0u;
+    const int d = (int)((key[it] >> shift) & 0xFF);
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const bool bit = (d >> b) & 1;
+      const uint64_t m = __ballot(bit);
+      peers &= bit ? m : ~m;
+    }
+    int prior = 0;
+    if (valid) prior = wc[w][d];
+    const int below = __popcll(peers & lt);
+    rank[it] = prior + below;
+    // the lowest lane of each digit group advances the running count
+    if (valid && below == 0) wc[w][d] = prior + __popcll(peers);
+  }
+  __syncthreads();
+  {
+    const int t = threadIdx.x;
+    int run = hist[(int64_t)t * nblocks + blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int c = wc[k][t];
+      wc[k][t] = run;
+      run += c;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < kSortItems; ++it) {
+    const int64_t idx = start + it * 64 + lane;
+    if (idx < n) {
+      const int d = (int)((key[it] >> shift) & 0xFF);
+      const int64_t dst = (int64_t)wc[w][d] + rank[it];
+      keys_out[dst] = key[it];
+      vals_out[dst] = val[it];
+    }
+  }
+}
+
+template <typename K>
+hipError_t radix_sort(K* k0, uint32_t* v0, K* k1, uint32_t* v1, const int64_t* count, int64_t cap, int bits,
+                      int32_t* hist, int32_t* hist_tmp, int* out_parity, hipStream_t s) {
+  const int64_t nb = div_up(cap > 0 ? cap : 1, kSortTile);
+  const int passes = (bits + 7) / 8;
+  K* ki = k0; uint32_t* vi = v0; K* ko = k1; uint32_t* vo = v1;
+  for (int p = 0; p < passes; ++p) {
+    const int shift = 8 * p;
+    hipLaunchKernelGGL((k_radix_hist<K>), dim3((unsigned)nb), dim3(kSortThreads), 0, s, ki, count, cap, shift, hist, nb);
+    hipError_t e = exclusive_scan<int32_t, int32_t>(hist, 256 * nb, hist, hist_tmp, nullptr, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_radix_scatter<K>), dim3((unsigned)nb), dim3(kSortThreads), 0, s, ki, vi, ko, vo, count, cap,
+                       shift, hist, nb);
+    K* tk = ki; ki = ko; ko = tk;
+    uint32_t* tv = vi; vi = vo; vo = tv;
+  }
+  *out_parity = passes & 1;
+  return hipGetLastError();
+}
+
+template hipError_t radix_sort<uint64_t>(uint64_t*, uint32_t*, uint64_t*, uint32_t*, const int64_t*, int64_t, int,
+                                         int32_t*, int32_t*, int*, hipStream_t);
+template hipError_t radix_sort<uint32_t>(uint32_t*, uint32_t*, uint32_t*, uint32_t*, const int64_t*, int64_t, int,
+                                         int32_t*, int32_t*, int*, hipStream_t);
+
+// ------------------------------------------------------------------------- tiles
+
+__global__ void k_cam_table(const sof_camera* cams, int n_cams, int tile, CamInfo* out, StatusBlock* status) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  int32_t toff = 0;
+  int64_t poff = 0;
+  for (int c = 0; c < n_cams; ++c) {
+    CamInfo ci;
+    ci.tiles_x = (cams[c].width + tile - 1) / tile;
+    ci.tiles_y = (cams[c].height + tile - 1) / tile;
+    ci.tile_off = toff;
+    ci.pix_off = poff;
+    ci.pad = 0; ci.pad2 = 0;
+    out[c] = ci;
+    toff += ci.tiles_x * ci.tiles_y;
+    poff += (int64_t)cams[c].width * cams[c].height;
+  }
+  CamInfo end;
+  end.tile_off = toff; end.pix_off = poff; end.tiles_x = end.tiles_y = 0; end.pad = 0; end.pad2 = 0;
+  out[n_cams] = end;
+  status->count = 0;
+  status->flags = 0;
+}
+
+__global__ __launch_bounds__(256) void k_count(const short4* rect, int64_t vn, int tile, int32_t* counts) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= vn) return;
+  const short4 r = rect[idx];
+  int c = 0;
+  if (r.x <= r.z && r.y <= r.w) c = (r.z / tile - r.x / tile + 1) * (r.w / tile - r.y / tile + 1);
+  counts[idx] = c;
+}
+
+__global__ __launch_bounds__(256) void k_emit(const short4* rect, const float4* geom, const float* zmin, int64_t n,
+                                              int64_t vn, int tile, const CamInfo* cams, const int32_t* counts,
+                                              const int64_t* offsets, int64_t cap, int query_keys, uint64_t* keys,
+                                              uint32_t* vals, int32_t* gid, StatusBlock* status) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= vn) return;
+  const int cnt = counts[idx];
+  if (cnt == 0) return;
+  const short4 r = rect[idx];
+  const int c = (int)(idx / n);
+  const int32_t g = (int32_t)(idx - (int64_t)c * n);
+  const CamInfo ci = cams[c];
+  const uint32_t k32 = query_keys ? float_order_bits(zmin[idx]) : float_order_bits(geom[4 * idx + 3].x);
+  int64_t e = offsets[idx];
+  if (e + cnt > cap) atomicOr(&status->flags, 1);
+  for (int ty = r.y / tile; ty <= r.w / tile; ++ty)
+    for (int tx = r.x / tile; tx <= r.z / tile; ++tx, ++e) {
+      if (e >= cap) return;
+      const uint64_t t = (uint64_t)(ci.tile_off + ty * ci.tiles_x + tx);
+      keys[e] = (t << 32) | (uint64_t)k32;
+      vals[e] = (uint32_t)e;
+      gid[e] = g;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_fill_ranges(int2* ranges, int64_t n_tiles) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n_tiles) ranges[i] = make_int2(0, 0);
+}
+
+__global__ __launch_bounds__(256) void k_ranges(const uint64_t* keys, const int64_t* count, int64_t cap, int2* ranges) {
+  const int64_t n = live_count(count, cap);
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t t = (uint32_t)(keys[i] >> 32);
+  if (i == 0 || (uint32_t)(keys[i - 1] >> 32) != t) ranges[t].x = (int)i;
+  if (i == n - 1 || (uint32_t)(keys[i + 1] >> 32) != t) ranges[t].y = (int)(i + 1);
+}
+
+hipError_t launch_bin_sort(int64_t n, const sof_camera* d_cams, int n_cams, int64_t n_tiles, int tile, int64_t cap,
+                           int query_keys, const void* proj, void* bins, hipStream_t s, int* parity) {
+  const int64_t vn = n * (int64_t)n_cams;
+  const ProjLayout P = ProjLayout::make(vn);
+  const BinsLayout B = BinsLayout::make(vn, n_cams, cap, n_tiles);
+  const char* pb = (const char*)proj;
+  char* bb = (char*)bins;
+  StatusBlock* status = (StatusBlock*)(bb + B.status);
+  CamInfo* cams = (CamInfo*)(bb + B.cams);
+  int32_t* counts = (int32_t*)(bb + B.counts);
+  int64_t* offsets = (int64_t*)(bb + B.offsets);
+  int64_t* scan_tmp = (int64_t*)(bb + B.scan_tmp);
+  uint64_t* k0 = (uint64_t*)(bb + B.keys0);
+  uint64_t* k1 = (uint64_t*)(bb + B.keys1);
+  uint32_t* v0 = (uint32_t*)(bb + B.vals0);
+  uint32_t* v1 = (uint32_t*)(bb + B.vals1);
+  int32_t* gid = (int32_t*)(bb + B.gid);
+  int32_t* hist = (int32_t*)(bb + B.hist);
+  int32_t* hist_tmp = (int32_t*)(bb + B.hist_tmp);
+  int2* ranges = (int2*)(bb + B.ranges);
+  const short4* rect = (const short4*)(pb + P.rect);
+  const float4* geom = (const float4*)(pb + P.geom);
+  const float* zmin = (const float*)(pb + P.zmin);
+
+  hipLaunchKernelGGL(k_cam_table, dim3(1), dim3(64), 0, s, d_cams, n_cams, tile, cams, status);
+  const int th = 256;
+  if (vn > 0) {
+    hipLaunchKernelGGL(k_count, dim3((unsigned)div_up(vn, th)), dim3(th), 0, s, rect, vn, tile, counts);
+  }
+  hipError_t e = exclusive_scan<int32_t, int64_t>(counts, vn, offsets, scan_tmp, &status->count, s);
+  if (e != hipSuccess) return e;
+  if (vn > 0) {
+    hipLaunchKernelGGL(k_emit, dim3((unsigned)div_up(vn, th)), dim3(th), 0, s, rect, geom, zmin, n, vn, tile, cams,
+                       counts, offsets, cap, query_keys, k0, v0, gid, status);
+  }
+  const int bits = 32 + bits_for(n_tiles);
+  e = radix_sort<uint64_t>(k0, v0, k1, v1, &status->count, cap, bits, hist, hist_tmp, parity, s);
+  if (e != hipSuccess) return e;
+  const uint64_t* ks = *parity ? k1 : k0;
+  hipLaunchKernelGGL(k_fill_ranges, dim3((unsigned)div_up(n_tiles > 0 ? n_tiles : 1, th)), dim3(th), 0, s, ranges, n_tiles);
+  if (cap > 0) {
+    hipLaunchKernelGGL(k_ranges, dim3((unsigned)div_up(cap, th)), dim3(th), 0, s, ks, &status->count, cap, ranges);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace sof

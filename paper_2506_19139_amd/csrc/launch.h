@@ -1,0 +1,81 @@
+// Host-side launch helpers implemented in the individual kernel files.
+#pragma once
+
+#include "sof_internal.h"
+
+namespace sof {
+
+template <typename Tin, typename Tout>
+hipError_t exclusive_scan(const Tin* in, int64_t n, Tout* out, Tout* tmp, int64_t* total, hipStream_t s);
+
+template <typename K>
+hipError_t radix_sort(K* k0, uint32_t* v0, K* k1, uint32_t* v1, const int64_t* count, int64_t cap, int bits,
+                      int32_t* hist, int32_t* hist_tmp, int* out_parity, hipStream_t s);
+
+hipError_t launch_project(const sof_gaussians* g, const sof_camera* d_cams, int n_cams, float near_plane,
+                          void* proj, hipStream_t stream);
+
+// parity: which of the two key/value buffers holds the sorted instances (0 or 1).
+hipError_t launch_bin_sort(int64_t n, const sof_camera* d_cams, int n_cams, int64_t n_tiles, int tile, int64_t cap,
+                           int query_keys, const void* proj, void* bins, hipStream_t s, int* parity);
+
+struct RenderFwdArgs {
+  int64_t n;
+  const sof_camera* cams;
+  const CamInfo* cam_info;
+  int n_cams;
+  float near_plane;
+  float bg[3];
+  uint32_t flags;
+  const float4* geom;
+  const float4* app;
+  const int2* ranges;
+  const uint32_t* vals;     // sorted instance -> emission index
+  const int32_t* gid;       // emission index -> Gaussian
+  float* rgb;
+  float* acc;
+  float* depth;
+  float* normal;
+  float* aux;
+};
+
+struct RenderBwdArgs {
+  RenderFwdArgs f;
+  const float4* bwdr;
+  const float* out_rgb;
+  const float* out_normal;
+  const float* d_rgb;
+  const float* d_acc;
+  const float* d_depth;
+  const float* d_normal;
+  float* grads;             // [cap, 16] per emission index
+};
+
+hipError_t launch_render_fwd(const RenderFwdArgs& a, int tile, int window, int64_t n_tiles, hipStream_t s);
+hipError_t launch_render_bwd(const RenderBwdArgs& a, int tile, int window, int64_t n_tiles, hipStream_t s);
+bool render_supported(int tile, int window);
+
+struct ProjectBwdArgs {
+  const float* means;
+  const float* scales;
+  const float* quats;
+  const float* opac;
+  const float* sh;
+  int sh_degree;
+  int64_t n;
+  const sof_camera* cams;
+  int n_cams;
+  const int32_t* counts;
+  const int64_t* offsets;
+  const int64_t* count_total;
+  int64_t cap;
+  const float* grads;
+  float* d_means;
+  float* d_scales;
+  float* d_quats;
+  float* d_opac;
+  float* d_sh;
+};
+hipError_t launch_project_bwd(const ProjectBwdArgs& a, hipStream_t s);
+
+}  // namespace sof

@@ -1,0 +1,282 @@
+// Backward rasteriser: the adjoint of render_fwd, without per-sample state.
+//
+// Each lane replays its pixel's forward order exactly (same staging, candidate test and
+// window code), recomputing the transmittance T_j front to back.  Contributions behind j
+// come from the stored totals: for F in {colour, normal}, dF/dalpha_j = T_j f_j -
+// (F_total - F_<=j) / (1 - alpha_j); d acc / d alpha_j = T_end / (1 - alpha_j).
+// The exact-depth correction (App. A.3) is either treated as a constant, as in the paper
+// (d depth = |d| d s*_k), or differentiated fully (SOF_DEPTH_GRAD_FULL), which adds a term
+// through T_k to every Gaussian in front of the crossing.
+//
+// Gradients are taken with respect to the camera-space mean mu_c and precision P_c of the
+// emitted Gaussian: with r = mu_c - s* d the peak-to-mean offset,
+//   dq*/dmu = 2 P r,  dq*/dP = r r^T,  ds*/dmu = P d / A,  ds*/dP = sym(d r^T) / A,
+//   dA/dP = d d^T,  A = d^T P d, d = (x_n, y_n, 1).
+// Per lane the 16 partials (dmu 3, dP 6, do, dcolour 3, dnormal 3) are added into LDS slots
+// of the instance (two batches of slots stay resident); slots are written to the
+// per-instance buffer once, in list order, and the rare emission of an entry older than
+// two batches adds to the buffer atomically.  A separate kernel reduces the per-instance
+// partials of each Gaussian in a fixed order.
+#include "render_common.h"
+
+namespace sof {
+
+struct PixBwd {
+  float T;
+  float cr, cg, cb, nx, ny, nz;   // prefix sums of w c and w n
+  int emitted, n_emit;
+  bool done, crossed;
+};
+
+template <int TS, int W>
+__global__ __launch_bounds__(TS * TS) void k_render_bwd(RenderBwdArgs A) {
+  constexpr int NT = TS * TS;
+  constexpr int B = NT < 256 ? NT : 256;         // list entries staged per batch
+  constexpr int NS = 2 * B;                      // resident gradient slots (two batches)
+  __shared__ StageEntry stage[B];
+  __shared__ float gsl[kGradFields * NS];
+  const RenderFwdArgs& a = A.f;
+  const int tile = blockIdx.x;
+  const int c = find_cam(a.cam_info, a.n_cams, tile);
+  const CamInfo ci = a.cam_info[c];
+  const sof_camera& cam = a.cams[c];
+  const int width = cam.width, height = cam.height;
+  const int lt = tile - ci.tile_off;
+  const int tx = lt % ci.tiles_x, ty = lt / ci.tiles_x;
+  const int lx = threadIdx.x % TS, ly = threadIdx.x / TS;
+  const int x0 = tx * TS, y0 = ty * TS;
+  const int px = x0 + lx, py = y0 + ly;
+  const bool inside = px < width && py < height;
+  const int2 rg = A.f.ranges[tile];
+  const int len = rg.y - rg.x;
+  const int64_t cam_base = (int64_t)c * a.n;
+  const float near_plane = a.near_plane;
+  const float ifx = 1.f / cam.fx, ify = 1.f / cam.fy;
+
+  for (int s = threadIdx.x; s < kGradFields * NS; s += NT) gsl[s] = 0.f;
+
+  // ---- per-pixel forward state and upstream gradients
+  const int64_t hw = (int64_t)width * height;
+  const int64_t pix = (int64_t)py * width + px;
+  float T_end = 1.f, Tk = 0.f;
+  int n_emit = 0, kgid = -1;
+  float fr = 0, fg = 0, fb = 0, fnx = 0, fny = 0, fnz = 0;
+  float gr = 0, gg = 0, gb = 0, ga = 0, gd = 0, gnx = 0, gny = 0, gnz = 0;
+  if (inside) {
+    const float* aux = a.aux + 4 * ci.pix_off;
+    T_end = aux[pix];
+    n_emit = __float_as_int(aux[hw + pix]);
+    kgid = __float_as_int(aux[2 * hw + pix]);
+    Tk = aux[3 * hw + pix];
+    const int64_t o3 = 3 * ci.pix_off;
+    fr = A.out_rgb[o3 + pix]; fg = A.out_rgb[o3 + hw + pix]; fb = A.out_rgb[o3 + 2 * hw + pix];
+    if (A.out_normal) { fnx = A.out_normal[o3 + pix]; fny = A.out_normal[o3 + hw + pix]; fnz = A.out_normal[o3 + 2 * hw + pix]; }
+    if (A.d_rgb) { gr = A.d_rgb[o3 + pix]; gg = A.d_rgb[o3 + hw + pix]; gb = A.d_rgb[o3 + 2 * hw + pix]; }
+    if (A.d_normal) { gnx = A.d_normal[o3 + pix]; gny = A.d_normal[o3 + hw + pix]; gnz = A.d_normal[o3 + 2 * hw + pix]; }
+    if (A.d_acc) ga = A.d_acc[ci.pix_off + pix];
+    if (A.d_depth) gd = A.d_depth[ci.pix_off + pix];
+  }
+  const float rx = (px + 0.5f - cam.cx) * ifx, ry = (py + 0.5f - cam.cy) * ify;
+  const float dn = sqrtf(fmaf(rx, rx, fmaf(ry, ry, 1.f)));
+
+  // ---- exact-depth terms of the crossing Gaussian (full mode)
+  const bool full = (a.flags & SOF_DEPTH_GRAD_FULL) && !(a.flags & SOF_DEPTH_MEDIAN);
+  float cT = 0.f, dq_k = 0.f, dA_k = 0.f, do_k = 0.f;
+  if (full && inside && kgid >= 0 && gd != 0.f) {
+    const int64_t vg = cam_base + kgid;
+    const float4 r0 = a.geom[4 * vg], r1 = a.geom[4 * vg + 1], r2 = a.geom[4 * vg + 2], r3 = a.geom[4 * vg + 3];
+    const float2 d = pixel_offset(r0, px, py);
+    const Quad q = quad_terms(r1.x, r1.y, r1.z, r1.w, r2.x, r2.y, r2.z, r2.w, d.x, d.y);
+    const float x = fmaxf(q.num / q.den, 0.f);
+    const float g = (Tk - 0.5f) / (Tk * r3.y);
+    const float L = fmaxf(2.f * (-x * kLn2 - logf(g)), 0.f);
+    const float Am = r3.w * q.den;
+    const float S = sqrtf(L / Am);
+    if (S > 1e-7f * r3.x) {
+      const float inv = gd * dn / (S * Am);
+      cT = inv * (1.f / (Tk - 0.5f) - 1.f / Tk);
+      dq_k = 0.5f * inv;
+      dA_k = 0.5f * gd * dn * S / Am;
+      do_k = -inv / r3.y;
+    }
+  }
+
+  PixBwd p;
+  p.T = 1.f; p.cr = p.cg = p.cb = 0.f; p.nx = p.ny = p.nz = 0.f;
+  p.emitted = 0; p.n_emit = n_emit; p.crossed = false;
+  p.done = !inside || n_emit == 0;
+  Window<W> win;
+  win.init();
+
+  // one emitted Gaussian: its gradient partials, into LDS or (old entries) the buffer
+  auto emit = [&](float al, uint32_t pos, int cur_b) {
+    const int i = rg.x + (int)pos;
+    const uint32_t e = A.f.vals[i];
+    const int32_t gid = A.f.gid[e];
+    const int64_t vg = cam_base + gid;
+    const float4 r0 = a.geom[4 * vg], r1 = a.geom[4 * vg + 1], r2 = a.geom[4 * vg + 2], r3 = a.geom[4 * vg + 3];
+    const float4 p0 = A.bwdr[2 * vg], p1 = A.bwdr[2 * vg + 1];
+    const float4 col = a.app[2 * vg], nrm = a.app[2 * vg + 1];
+    const float2 dd = pixel_offset(r0, px, py);
+    const float dx = dd.x, dy = dd.y;
+    const Quad q = quad_terms(r1.x, r1.y, r1.z, r1.w, r2.x, r2.y, r2.z, r2.w, dx, dy);
+    const float mz = r3.x, o = r3.y, aa = r3.w;
+    const float iden = 1.f / q.den;
+    const float x = fmaxf(q.num * iden, 0.f);
+    const float G = exp2f(-x);
+    const float sstar = mz * (1.f + q.b) * iden;
+
+    const float Tj = p.T;
+    const float w = al * Tj;
+    const float om = 1.f - al;
+    const float iom = 1.f / om;
+    p.cr = fmaf(w, col.x, p.cr); p.cg = fmaf(w, col.y, p.cg); p.cb = fmaf(w, col.z, p.cb);
+    p.nx = fmaf(w, nrm.x, p.nx); p.ny = fmaf(w, nrm.y, p.ny); p.nz = fmaf(w, nrm.z, p.nz);
+    float dal = gr * (col.x * Tj - (fr - p.cr) * iom) + gg * (col.y * Tj - (fg - p.cg) * iom) +
+                gb * (col.z * Tj - (fb - p.cb) * iom);
+    dal += gnx * (nrm.x * Tj - (fnx - p.nx) * iom) + gny * (nrm.y * Tj - (fny - p.ny) * iom) +
+           gnz * (nrm.z * Tj - (fnz - p.nz) * iom);
+    dal += ga * T_end * iom;
+    const float testT = Tj * om;
+    const bool is_k = !p.crossed && testT <= 0.5f;
+    if (!p.crossed && !is_k) dal -= cT * Tk * iom;
+    const bool clamped = o * G > kAlphaMax;
+    float dq = clamped ? 0.f : -0.5f * al * dal;
+    float dop = clamped ? 0.f : dal * G;
+    float ds = 0.f, dA = 0.f;
+    if (is_k) {
+      ds = gd * dn;
+      dq += dq_k;
+      dA = dA_k;
+      dop += do_k;
+      p.crossed = true;
+    }
+    p.T = testT;
+    // chain to the camera-space mean and precision
+    const float dnx = dx * ifx, dny = dy * ify;
+    const float dmx = p1.z, dmy = p1.w;
+    const float dvx = dmx + dnx, dvy = dmy + dny;               // d = (dvx, dvy, 1)
+    const float mzs = mz * (q.b + q.c) * iden;                  // mu_z - s*
+    const float rxv = mzs * dmx - sstar * dnx, ryv = mzs * dmy - sstar * dny, rzv = mzs;
+    const float P00 = p0.x, P01 = p0.y, P02 = p0.z, P11 = p0.w, P12 = p1.x, P22 = p1.y;
+    const float Prx = P00 * rxv + P01 * ryv + P02 * rzv;
+    const float Pry = P01 * rxv + P11 * ryv + P12 * rzv;
+    const float Prz = P02 * rxv + P12 * ryv + P22 * rzv;
+    const float Pdx = P00 * dvx + P01 * dvy + P02;
+    const float Pdy = P01 * dvx + P11 * dvy + P12;
+    const float Pdz = P02 * dvx + P12 * dvy + P22;
+    const float Am = aa * q.den;
+    const float sA = ds / Am, hA = 0.5f * sA, dq2 = 2.f * dq;
+    float gv[kGradFields];
+    gv[0] = dq2 * Prx + sA * Pdx;
+    gv[1] = dq2 * Pry + sA * Pdy;
+    gv[2] = dq2 * Prz + sA * Pdz;
+    gv[3] = dq * rxv * rxv + hA * 2.f * dvx * rxv + dA * dvx * dvx;
+    gv[4] = dq * rxv * ryv + hA * (dvx * ryv + rxv * dvy) + dA * dvx * dvy;
+    gv[5] = dq * rxv * rzv + hA * (dvx * rzv + rxv) + dA * dvx;
+    gv[6] = dq * ryv * ryv + hA * 2.f * dvy * ryv + dA * dvy * dvy;
+    gv[7] = dq * ryv * rzv + hA * (dvy * rzv + ryv) + dA * dvy;
+    gv[8] = dq * rzv * rzv + hA * 2.f * rzv + dA;
+    gv[9] = dop;
+    gv[10] = gr * w; gv[11] = gg * w; gv[12] = gb * w;
+    gv[13] = gnx * w; gv[14] = gny * w; gv[15] = gnz * w;
+    const int resident_from = (cur_b - 1) * B;
+    if ((int)pos >= resident_from) {
+      const int slot = (int)pos % NS;
+#pragma unroll
+      for (int f = 0; f < kGradFields; ++f) atomicAdd(&gsl[f * NS + slot], gv[f]);
+    } else {
+      float* dst = A.grads + (size_t)e * kGradFields;
+#pragma unroll
+      for (int f = 0; f < kGradFields; ++f) atomicAdd(dst + f, gv[f]);
+    }
+    if (++p.emitted >= p.n_emit) p.done = true;
+  };
+
+  // write the resident slots of batch b to the per-instance buffer and clear them
+  auto flush = [&](int b) {
+    if (b < 0 || threadIdx.x >= B) return;
+    const int pos = b * B + (int)threadIdx.x;
+    if (pos >= len) return;
+    const int slot = pos % NS;
+    const uint32_t e = A.f.vals[rg.x + pos];
+    float4* dst = (float4*)(A.grads + (size_t)e * kGradFields);
+#pragma unroll
+    for (int f4 = 0; f4 < kGradFields / 4; ++f4) {
+      dst[f4] = make_float4(gsl[(4 * f4) * NS + slot], gsl[(4 * f4 + 1) * NS + slot], gsl[(4 * f4 + 2) * NS + slot],
+                            gsl[(4 * f4 + 3) * NS + slot]);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) gsl[(4 * f4 + k) * NS + slot] = 0.f;
+    }
+  };
+
+  int cur_b = -1;
+  for (int bs = rg.x; bs < rg.y; bs += B) {
+    if (__syncthreads_count(!p.done) == 0) break;
+    ++cur_b;
+    flush(cur_b - 2);
+    const int i = bs + (int)threadIdx.x;
+    if (threadIdx.x < B && i < rg.y) {
+      const int32_t g = A.f.gid[A.f.vals[i]];
+      stage_entry(a.geom, cam_base + g, x0, y0, (uint32_t)(i - rg.x), &stage[threadIdx.x]);
+    }
+    __threadfence();
+    __syncthreads();
+    const int nb = min(B, rg.y - bs);
+    if (!p.done) {
+      for (int j = 0; j < nb; ++j) {
+        const StageEntry e = stage[j];
+        float key, al;
+        if (!eval_candidate(e, lx, ly, near_plane, key, al)) continue;
+        float ea;
+        uint32_t et;
+        if (win.push(key, al, __float_as_uint(e.tag), ea, et)) {
+          emit(ea, et, cur_b);
+          if (p.done) break;
+        }
+      }
+    }
+  }
+  if constexpr (W > 0) {
+#pragma unroll
+    for (int i = 0; i < W; ++i)
+      if (!p.done && i < win.count) emit(win.a[i], win.t[i], cur_b);
+  }
+  __syncthreads();
+  flush(cur_b - 1);
+  flush(cur_b);
+  // entries never staged (the whole tile finished early) get zero partials
+  for (int pos = (cur_b + 1) * B + (int)threadIdx.x; pos < len; pos += NT) {
+    float4* dst = (float4*)(A.grads + (size_t)A.f.vals[rg.x + pos] * kGradFields);
+#pragma unroll
+    for (int f4 = 0; f4 < kGradFields / 4; ++f4) dst[f4] = make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+}
+
+template <int TS>
+static hipError_t launch_bwd_ts(const RenderBwdArgs& a, int window, int64_t n_tiles, hipStream_t s) {
+  const dim3 grid((unsigned)n_tiles), block(TS * TS);
+  switch (window) {
+    case 0: hipLaunchKernelGGL((k_render_bwd<TS, 0>), grid, block, 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_render_bwd<TS, 1>), grid, block, 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_render_bwd<TS, 2>), grid, block, 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_render_bwd<TS, 4>), grid, block, 0, s, a); break;
+    case 8: hipLaunchKernelGGL((k_render_bwd<TS, 8>), grid, block, 0, s, a); break;
+    case 16: hipLaunchKernelGGL((k_render_bwd<TS, 16>), grid, block, 0, s, a); break;
+    case 32: hipLaunchKernelGGL((k_render_bwd<TS, 32>), grid, block, 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_render_bwd(const RenderBwdArgs& a, int tile, int window, int64_t n_tiles, hipStream_t s) {
+  if (n_tiles <= 0) return hipSuccess;
+  switch (tile) {
+    case 8: return launch_bwd_ts<8>(a, window, n_tiles, s);
+    case 16: return launch_bwd_ts<16>(a, window, n_tiles, s);
+    case 32: return launch_bwd_ts<32>(a, window, n_tiles, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace sof

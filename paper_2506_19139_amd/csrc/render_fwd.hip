@@ -1,0 +1,174 @@
+// Forward rasteriser: one workgroup per screen tile (TS x TS lanes, one pixel per lane).
+// The tile's list is staged through LDS in batches of TS*TS entries with one coalesced
+// 64-byte record load per lane; every lane then walks the batch from LDS (broadcast reads),
+// tests candidates, feeds its register window and blends what the window emits front to
+// back (Eq. (1)).  The workgroup leaves the list once no lane is still accumulating.
+// Outputs per pixel: colour, accumulated opacity, exact depth (Sec. 3.2), normal and the
+// replay state the backward pass needs.
+#include "render_common.h"
+
+namespace sof {
+
+struct PixFwd {
+  float T, r, g, b, nx, ny, nz, Tk;
+  int n_emit, k;
+  bool done;
+};
+
+__device__ inline void blend(PixFwd& p, float alpha, uint32_t gid, const float4* app, int64_t cam_base) {
+  const float test_T = p.T * (1.f - alpha);
+  if (test_T < kTMin) {
+    p.done = true;
+    return;
+  }
+  const float w = alpha * p.T;
+  const float4 c = app[2 * (cam_base + gid)];
+  const float4 nn = app[2 * (cam_base + gid) + 1];
+  p.r = fmaf(w, c.x, p.r);
+  p.g = fmaf(w, c.y, p.g);
+  p.b = fmaf(w, c.z, p.b);
+  p.nx = fmaf(w, nn.x, p.nx);
+  p.ny = fmaf(w, nn.y, p.ny);
+  p.nz = fmaf(w, nn.z, p.nz);
+  if (p.k < 0 && test_T <= 0.5f) {
+    p.k = (int)gid;
+    p.Tk = p.T;
+  }
+  p.T = test_T;
+  ++p.n_emit;
+}
+
+template <int TS, int W>
+__global__ __launch_bounds__(TS * TS) void k_render_fwd(RenderFwdArgs a) {
+  constexpr int NT = TS * TS;
+  constexpr int B = NT < 256 ? NT : 256;         // list entries staged per batch
+  __shared__ StageEntry stage[B];
+  const int tile = blockIdx.x;
+  const int c = find_cam(a.cam_info, a.n_cams, tile);
+  const CamInfo ci = a.cam_info[c];
+  const sof_camera& cam = a.cams[c];
+  const int width = cam.width, height = cam.height;
+  const int lt = tile - ci.tile_off;
+  const int tx = lt % ci.tiles_x, ty = lt / ci.tiles_x;
+  const int lx = threadIdx.x % TS, ly = threadIdx.x / TS;
+  const int x0 = tx * TS, y0 = ty * TS;
+  const int px = x0 + lx, py = y0 + ly;
+  const bool inside = px < width && py < height;
+  const int2 rg = a.ranges[tile];
+  const int64_t cam_base = (int64_t)c * a.n;
+  const float near_plane = a.near_plane;
+
+  PixFwd p;
+  p.T = 1.f; p.r = p.g = p.b = 0.f; p.nx = p.ny = p.nz = 0.f; p.Tk = 0.f; p.n_emit = 0; p.k = -1;
+  p.done = !inside;
+  Window<W> win;
+  win.init();
+
+  for (int bs = rg.x; bs < rg.y; bs += B) {
+    if (__syncthreads_count(!p.done) == 0) break;
+    const int i = bs + (int)threadIdx.x;
+    if (threadIdx.x < B && i < rg.y) {
+      const int32_t g = a.gid[a.vals[i]];
+      stage_entry(a.geom, cam_base + g, x0, y0, (uint32_t)g, &stage[threadIdx.x]);
+    }
+    __syncthreads();
+    const int nb = min(B, rg.y - bs);
+    if (!p.done) {
+      for (int j = 0; j < nb; ++j) {
+        const StageEntry e = stage[j];
+        float key, al;
+        if (!eval_candidate(e, lx, ly, near_plane, key, al)) continue;
+        float ea;
+        uint32_t et;
+        if (win.push(key, al, __float_as_uint(e.tag), ea, et)) {
+          blend(p, ea, et, a.app, cam_base);
+          if (p.done) break;
+        }
+      }
+    }
+  }
+  if constexpr (W > 0) {
+#pragma unroll
+    for (int i = 0; i < W; ++i)
+      if (!p.done && i < win.count) blend(p, win.a[i], win.t[i], a.app, cam_base);
+  }
+  if (!inside) return;
+
+  // exact depth of the 0.5 level set on the crossing Gaussian (Sec. 3.2, App. A.3)
+  const float rx = (px + 0.5f - cam.cx) / cam.fx, ry = (py + 0.5f - cam.cy) / cam.fy;
+  const float dn = sqrtf(fmaf(rx, rx, fmaf(ry, ry, 1.f)));
+  float depth = 0.f;
+  if (p.k >= 0) {
+    const int64_t vg = cam_base + p.k;
+    const float4 r0 = a.geom[4 * vg], r1 = a.geom[4 * vg + 1], r2 = a.geom[4 * vg + 2], r3 = a.geom[4 * vg + 3];
+    const float2 d = pixel_offset(r0, px, py);
+    const Quad q = quad_terms(r1.x, r1.y, r1.z, r1.w, r2.x, r2.y, r2.z, r2.w, d.x, d.y);
+    const float sstar = r3.x * (1.f + q.b) / q.den;
+    if (a.flags & SOF_DEPTH_MEDIAN) {
+      depth = dn * sstar;
+    } else {
+      const float x = fmaxf(q.num / q.den, 0.f);                 // K q*
+      const float g = (p.Tk - 0.5f) / (p.Tk * r3.y);
+      const float L = fmaxf(2.f * (-x * kLn2 - logf(g)), 0.f);  // 2 ln(G*/g)
+      const float A = r3.w * q.den;                              // d^T P d, d = (x_n, y_n, 1)
+      depth = dn * (sstar - sqrtf(L / A));
+    }
+  }
+  const int64_t hw = (int64_t)width * height;
+  const int64_t pix = (int64_t)py * width + px;
+  const float T = p.T;
+  if (a.rgb) {
+    float* o = a.rgb + 3 * ci.pix_off;
+    o[pix] = fmaf(a.bg[0], T, p.r);
+    o[hw + pix] = fmaf(a.bg[1], T, p.g);
+    o[2 * hw + pix] = fmaf(a.bg[2], T, p.b);
+  }
+  if (a.acc) a.acc[ci.pix_off + pix] = 1.f - T;
+  if (a.depth) a.depth[ci.pix_off + pix] = depth;
+  if (a.normal) {
+    float* o = a.normal + 3 * ci.pix_off;
+    o[pix] = p.nx;
+    o[hw + pix] = p.ny;
+    o[2 * hw + pix] = p.nz;
+  }
+  if (a.aux) {
+    float* o = a.aux + 4 * ci.pix_off;
+    o[pix] = T;
+    o[hw + pix] = __int_as_float(p.n_emit);
+    o[2 * hw + pix] = __int_as_float(p.k);
+    o[3 * hw + pix] = p.Tk;
+  }
+}
+
+template <int TS>
+static hipError_t launch_fwd_ts(const RenderFwdArgs& a, int window, int64_t n_tiles, hipStream_t s) {
+  const dim3 grid((unsigned)n_tiles), block(TS * TS);
+  switch (window) {
+    case 0: hipLaunchKernelGGL((k_render_fwd<TS, 0>), grid, block, 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_render_fwd<TS, 1>), grid, block, 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_render_fwd<TS, 2>), grid, block, 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_render_fwd<TS, 4>), grid, block, 0, s, a); break;
+    case 8: hipLaunchKernelGGL((k_render_fwd<TS, 8>), grid, block, 0, s, a); break;
+    case 16: hipLaunchKernelGGL((k_render_fwd<TS, 16>), grid, block, 0, s, a); break;
+    case 32: hipLaunchKernelGGL((k_render_fwd<TS, 32>), grid, block, 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+bool render_supported(int tile, int window) {
+  const bool w = window == 0 || window == 1 || window == 2 || window == 4 || window == 8 || window == 16 || window == 32;
+  return w && (tile == 8 || tile == 16 || tile == 32);
+}
+
+hipError_t launch_render_fwd(const RenderFwdArgs& a, int tile, int window, int64_t n_tiles, hipStream_t s) {
+  if (n_tiles <= 0) return hipSuccess;
+  switch (tile) {
+    case 8: return launch_fwd_ts<8>(a, window, n_tiles, s);
+    case 16: return launch_fwd_ts<16>(a, window, n_tiles, s);
+    case 32: return launch_fwd_ts<32>(a, window, n_tiles, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace sof

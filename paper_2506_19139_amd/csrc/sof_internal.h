@@ -1,0 +1,132 @@
+// Internal layouts of the caller-owned buffers and helpers shared by the HIP kernels and
+// the C-ABI host code.  Nothing here is part of the public interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/sof.h"
+
+namespace sof {
+
+constexpr int kMaxShCoeffs = 16;
+constexpr float kAlphaMin = 1.0f / 255.0f;   // a contribution below this is skipped
+constexpr float kAlphaMax = 0.99f;           // alpha clamp
+constexpr float kTMin = 1e-4f;               // blending stops before T would drop below
+constexpr float kHalfLog2e = 0.72134752044448170368f;   // 0.5 * log2(e): exp(-q/2) = exp2(-K q)
+constexpr float kLn2 = 0.69314718055994530942f;
+constexpr int kGradFields = 16;              // per-instance gradient partials
+constexpr size_t kAlign = 256;
+
+inline __host__ __device__ size_t align_up(size_t x, size_t a = kAlign) { return (x + a - 1) / a * a; }
+
+// ------------------------------------------------------------------------------------
+// proj buffer: per (camera, Gaussian) records, index vg = cam * n + gaussian.
+//
+// geom (16 floats, 64 B) -- everything the per-pixel loop reads, in pixel units:
+//   [0] u_int (int bits)  [1] u_frac   [2] v_int (int bits)  [3] v_frac
+//       projected centre u = fx mu_x/mu_z + cx split into integer and fraction so that a
+//       pixel offset is formed without cancellation
+//   [4] gx  [5] gy                  b' = gx dx + gy dy
+//   [6] cxx [7] 2 cxy [8] cyy       c' = cxx dx^2 + 2cxy dx dy + cyy dy^2
+//   [9] mxx [10] 2 mxy [11] myy     n' = mxx dx^2 + ...           (includes 0.5 log2 e)
+//   [12] mu_z  [13] opacity  [14] log2(255 o)  [15] a = dm^T P dm
+// with (dx, dy) the pixel-centre offset from (u, v), P the camera-space precision,
+// dm = (mu_x/mu_z, mu_y/mu_z, 1).  Along the pixel ray d = dm + (dx/fx, dy/fy, 0):
+//   den' = 1 + 2 b' + c' = d^T P d / a,   z-depth of the peak s* = mu_z (1 + b') / den',
+//   G* = exp2(-n'/den'),   q* = n' / (den' 0.5 log2 e).
+// app (8 floats): r g b (linear, clamped >= 0), pad, nx ny nz (world normal), pad
+// bwdr (8 floats): P00 P01 P02 P11 P12 P22 dm_x dm_y   (camera-space precision)
+// rect (4 x int16): x0 y0 x1 y1 inclusive pixel rectangle; x0 > x1 when not live
+// zmin (float): mu_z - E sqrt(Sigma_zz), the smallest view z on the E-ellipsoid
+// ------------------------------------------------------------------------------------
+struct ProjLayout {
+  size_t geom, app, bwdr, rect, zmin, total;
+  static __host__ __device__ ProjLayout make(int64_t vn) {
+    ProjLayout L;
+    size_t o = 0;
+    L.geom = o; o = align_up(o + (size_t)vn * 64);
+    L.app = o;  o = align_up(o + (size_t)vn * 32);
+    L.bwdr = o; o = align_up(o + (size_t)vn * 32);
+    L.rect = o; o = align_up(o + (size_t)vn * 8);
+    L.zmin = o; o = align_up(o + (size_t)vn * 4);
+    L.total = o;
+    return L;
+  }
+};
+
+// Per-camera table written on the device by sof_bin_sort (read by render kernels).
+struct CamInfo {
+  int32_t tile_off;   // first global tile id of this camera
+  int32_t tiles_x, tiles_y;
+  int32_t pad;
+  int64_t pix_off;    // first pixel of this camera in concatenated images
+  int64_t pad2;
+};
+
+// Device status block at offset 0 of `bins` (and of the query schedule buffer).
+struct StatusBlock {
+  int64_t count;      // instances requested
+  int32_t flags;      // bit 0: capacity exceeded
+  int32_t pad;
+  int64_t aux[30];
+};
+
+constexpr int kSortItems = 8;                    // keys per thread in a radix sort tile
+constexpr int kSortThreads = 256;
+constexpr int kSortTile = kSortItems * kSortThreads;
+constexpr int kScanItems = 16;
+constexpr int kScanThreads = 256;
+constexpr int kScanChunk = kScanItems * kScanThreads;
+
+inline __host__ __device__ int64_t div_up(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// bins buffer layout.
+struct BinsLayout {
+  size_t status, cams, counts, offsets, scan_tmp, keys0, keys1, vals0, vals1, gid, hist, hist_tmp,
+      ranges, total;
+  int64_t vn, cap, n_tiles, sort_blocks;
+  static __host__ __device__ BinsLayout make(int64_t vn, int32_t n_cams, int64_t cap, int64_t n_tiles) {
+    BinsLayout L;
+    L.vn = vn; L.cap = cap; L.n_tiles = n_tiles;
+    L.sort_blocks = div_up(cap > 0 ? cap : 1, kSortTile);
+    size_t o = 0;
+    L.status = o;   o = align_up(o + sizeof(StatusBlock));
+    L.cams = o;     o = align_up(o + (size_t)(n_cams + 1) * sizeof(CamInfo));
+    L.counts = o;   o = align_up(o + (size_t)vn * 4);
+    L.offsets = o;  o = align_up(o + (size_t)vn * 8);
+    L.scan_tmp = o; o = align_up(o + (size_t)(div_up(vn > 0 ? vn : 1, kScanChunk) + 1) * 8);
+    L.keys0 = o;    o = align_up(o + (size_t)cap * 8);
+    L.keys1 = o;    o = align_up(o + (size_t)cap * 8);
+    L.vals0 = o;    o = align_up(o + (size_t)cap * 4);
+    L.vals1 = o;    o = align_up(o + (size_t)cap * 4);
+    L.gid = o;      o = align_up(o + (size_t)cap * 4);
+    const int64_t hn = 256 * L.sort_blocks;
+    L.hist = o;     o = align_up(o + (size_t)hn * 4);
+    L.hist_tmp = o; o = align_up(o + (size_t)(div_up(hn, kScanChunk) + 1) * 8);
+    L.ranges = o;   o = align_up(o + (size_t)(n_tiles > 0 ? n_tiles : 1) * 8);
+    L.total = o;
+    return L;
+  }
+};
+
+// Number of bits needed to hold values 0..v-1 (at least 1).
+inline __host__ __device__ int bits_for(int64_t v) {
+  int b = 1;
+  while ((int64_t(1) << b) < v) ++b;
+  return b;
+}
+
+inline __host__ __device__ uint32_t fbits(float f) {
+  union { float f; uint32_t u; } x;
+  x.f = f;
+  return x.u;
+}
+
+// Order-preserving map from float to uint32 (for keys that may be negative).
+inline __host__ __device__ uint32_t float_order_bits(float f) {
+  uint32_t u = fbits(f);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+}  // namespace sof

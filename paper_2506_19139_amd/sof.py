@@ -1,0 +1,383 @@
+"""Thin ctypes binding of libsof.so.
+
+Only argument marshalling lives here: every step of the hot path runs in the HIP kernels
+behind the C ABI.  PyTorch supplies device memory and the current stream.  The library
+must be built (``python -m paper_2506_19139_amd.build``); nothing falls back to another
+implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsof.so")
+
+SOF_OK, SOF_E_ARG, SOF_E_WORKSPACE, SOF_E_CAPACITY, SOF_E_HIP, SOF_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
+SOF_DEPTH_MEDIAN = 1 << 0
+SOF_DEPTH_GRAD_FULL = 1 << 1
+SOF_QUERY_KEYS = 1 << 2
+
+WINDOWS = (0, 1, 2, 4, 8, 16, 32)
+TILES = (8, 16, 32)
+
+
+class SofError(RuntimeError):
+    pass
+
+
+class CGaussians(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("sh_degree", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("means", ctypes.c_void_p), ("scales", ctypes.c_void_p), ("quats", ctypes.c_void_p),
+                ("opacities", ctypes.c_void_p), ("sh", ctypes.c_void_p)]
+
+
+class CCamera(ctypes.Structure):
+    _fields_ = [("R", ctypes.c_float * 9), ("t", ctypes.c_float * 3), ("fx", ctypes.c_float),
+                ("fy", ctypes.c_float), ("cx", ctypes.c_float), ("cy", ctypes.c_float),
+                ("width", ctypes.c_int32), ("height", ctypes.c_int32)]
+
+
+class COptions(ctypes.Structure):
+    _fields_ = [("tile", ctypes.c_int32), ("window", ctypes.c_int32), ("near_plane", ctypes.c_float),
+                ("bg", ctypes.c_float * 3), ("flags", ctypes.c_uint32), ("reserved", ctypes.c_int32),
+                ("capacity", ctypes.c_int64)]
+
+
+assert ctypes.sizeof(CCamera) == 72
+
+_lib = None
+_P = ctypes.c_void_p
+_SZ = ctypes.POINTER(ctypes.c_size_t)
+
+_SIGS = {
+    "sof_workspace_size": (ctypes.c_int, [ctypes.c_int64, _P, ctypes.c_int32, _P, _SZ, _SZ, _SZ]),
+    "sof_read_status_offset": (ctypes.c_size_t, []),
+    "sof_project": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, _P, _P, ctypes.c_size_t, _P]),
+    "sof_bin_sort": (ctypes.c_int, [ctypes.c_int64, _P, _P, ctypes.c_int32, _P, _P, ctypes.c_size_t, _P,
+                                    ctypes.c_size_t, _P]),
+    "sof_render_fwd": (ctypes.c_int, [ctypes.c_int64, _P, _P, ctypes.c_int32, _P, _P, ctypes.c_size_t, _P,
+                                      ctypes.c_size_t, _P, _P, _P, _P, _P, _P]),
+    "sof_render_bwd": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, _P, _P, ctypes.c_size_t, _P, ctypes.c_size_t,
+                                      _P, _P, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P, _P, _P, _P, _P, _P]),
+    "sof_query_workspace_size": (ctypes.c_int, [ctypes.c_int64, _P, ctypes.c_int32, _P, ctypes.c_int64,
+                                                ctypes.c_int64, _SZ, _SZ, _SZ]),
+    "sof_opacity_query": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, _P, _P, ctypes.c_int64, ctypes.c_int64,
+                                         _P, _P, ctypes.c_size_t, _P, ctypes.c_size_t, _P, ctypes.c_size_t, _P]),
+    "sof_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+}
+
+EXPORTED = tuple(_SIGS)
+
+
+def lib():
+    """Load libsof.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise SofError(f"{LIB_PATH} is missing: build it with `python -m paper_2506_19139_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(code, what):
+    if code != SOF_OK:
+        msg = lib().sof_strerror(code).decode()
+        raise SofError(f"{what}: {msg} ({code})")
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+# ------------------------------------------------------------------------------ inputs
+
+@dataclass
+class Gaussians:
+    means: torch.Tensor
+    scales: torch.Tensor
+    quats: torch.Tensor
+    opac: torch.Tensor
+    sh: torch.Tensor
+    sh_degree: int
+
+    @staticmethod
+    def from_numpy(d, device="cuda"):
+        f = lambda k: torch.from_numpy(np.ascontiguousarray(d[k], np.float32)).to(device)
+        return Gaussians(f("means"), f("scales"), f("quats"), f("opac").reshape(-1), f("sh"), int(d["sh_degree"]))
+
+    @property
+    def n(self):
+        return int(self.means.shape[0])
+
+    def c_struct(self):
+        for t in (self.means, self.scales, self.quats, self.opac, self.sh):
+            if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+                raise SofError("Gaussian parameters must be contiguous float32 CUDA tensors")
+        return CGaussians(self.n, self.sh_degree, 0, self.means.data_ptr(), self.scales.data_ptr(),
+                          self.quats.data_ptr(), self.opac.data_ptr(), self.sh.data_ptr())
+
+
+class Cameras:
+    """Host and device copies of an array of sof_camera."""
+
+    def __init__(self, cams, device="cuda"):
+        if isinstance(cams, dict):
+            cams = [cams]
+        self.list = list(cams)
+        n = len(self.list)
+        self.host = (CCamera * n)()
+        for i, c in enumerate(self.list):
+            R = np.asarray(c["R"], np.float32).reshape(9)
+            t = np.asarray(c["t"], np.float32).reshape(3)
+            self.host[i].R[:] = [float(x) for x in R]
+            self.host[i].t[:] = [float(x) for x in t]
+            self.host[i].fx, self.host[i].fy = float(c["fx"]), float(c["fy"])
+            self.host[i].cx, self.host[i].cy = float(c["cx"]), float(c["cy"])
+            self.host[i].width, self.host[i].height = int(c["width"]), int(c["height"])
+        raw = np.frombuffer(bytes(self.host), dtype=np.uint8).copy()
+        self.device = torch.from_numpy(raw).to(device)
+
+    def __len__(self):
+        return len(self.list)
+
+    @property
+    def sizes(self):
+        return [(int(c["width"]), int(c["height"])) for c in self.list]
+
+    @property
+    def n_pixels(self):
+        return sum(w * h for w, h in self.sizes)
+
+    def hp(self):
+        return ctypes.cast(self.host, ctypes.c_void_p)
+
+    def dp(self):
+        return ctypes.c_void_p(self.device.data_ptr())
+
+
+@dataclass
+class Options:
+    tile: int = 16
+    window: int = 8
+    near_plane: float = 0.2
+    bg: tuple = (0.0, 0.0, 0.0)
+    flags: int = 0
+    capacity: int = 0
+
+    def c_struct(self):
+        o = COptions()
+        o.tile, o.window, o.near_plane = int(self.tile), int(self.window), float(self.near_plane)
+        o.bg[:] = [float(x) for x in self.bg]
+        o.flags, o.reserved, o.capacity = int(self.flags), 0, int(self.capacity)
+        return o
+
+
+# ------------------------------------------------------------------------------ raw calls
+
+def workspace_size(n, cams: Cameras, opts: Options):
+    p, b, g = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
+    o = opts.c_struct()
+    _check(lib().sof_workspace_size(n, cams.hp(), len(cams), ctypes.byref(o), ctypes.byref(p), ctypes.byref(b),
+                                    ctypes.byref(g)), "sof_workspace_size")
+    return p.value, b.value, g.value
+
+
+def project(g: Gaussians, cams: Cameras, opts: Options, proj: torch.Tensor):
+    gs, o = g.c_struct(), opts.c_struct()
+    _check(lib().sof_project(ctypes.byref(gs), cams.hp(), cams.dp(), len(cams), ctypes.byref(o), _ptr(proj),
+                             proj.numel(), _stream()), "sof_project")
+
+
+def bin_sort(n, cams: Cameras, opts: Options, proj, bins):
+    o = opts.c_struct()
+    _check(lib().sof_bin_sort(n, cams.hp(), cams.dp(), len(cams), ctypes.byref(o), _ptr(proj), proj.numel(),
+                              _ptr(bins), bins.numel(), _stream()), "sof_bin_sort")
+
+
+def render_fwd(n, cams: Cameras, opts: Options, proj, bins, rgb=None, acc=None, depth=None, normal=None, aux=None):
+    o = opts.c_struct()
+    _check(lib().sof_render_fwd(n, cams.hp(), cams.dp(), len(cams), ctypes.byref(o), _ptr(proj), proj.numel(),
+                                _ptr(bins), bins.numel(), _ptr(rgb), _ptr(acc), _ptr(depth), _ptr(normal), _ptr(aux),
+                                _stream()), "sof_render_fwd")
+
+
+def render_bwd(g: Gaussians, cams: Cameras, opts: Options, proj, bins, rgb, normal, aux, d_rgb, d_acc, d_depth,
+               d_normal, grads, d_means, d_scales, d_quats, d_opac, d_sh):
+    gs, o = g.c_struct(), opts.c_struct()
+    _check(lib().sof_render_bwd(ctypes.byref(gs), cams.hp(), cams.dp(), len(cams), ctypes.byref(o), _ptr(proj),
+                                proj.numel(), _ptr(bins), bins.numel(), _ptr(rgb), _ptr(normal), _ptr(aux),
+                                _ptr(d_rgb), _ptr(d_acc), _ptr(d_depth), _ptr(d_normal), _ptr(grads),
+                                grads.numel() if grads is not None else 0, _ptr(d_means), _ptr(d_scales),
+                                _ptr(d_quats), _ptr(d_opac), _ptr(d_sh), _stream()), "sof_render_bwd")
+
+
+def read_status(buf: torch.Tensor):
+    """(instances requested, status flags) from a bins / schedule buffer (synchronises)."""
+    off = lib().sof_read_status_offset()
+    raw = buf[off:off + 16].cpu().numpy()
+    return int(raw[:8].view(np.int64)[0]), int(raw[8:12].view(np.int32)[0])
+
+
+# ------------------------------------------------------------------------------ views of bins
+
+def sorted_instances(bins: torch.Tensor, n, cams: Cameras, opts: Options):
+    """Debug view of the sorted tile lists: (keys uint64, gaussian ids, ranges[n_tiles,2]) as
+    numpy arrays (synchronises).  Layout mirrors the internal bins layout."""
+    vn = n * len(cams)
+    n_tiles = sum(((w + opts.tile - 1) // opts.tile) * ((h + opts.tile - 1) // opts.tile) for w, h in cams.sizes)
+    L = _bins_layout(vn, len(cams), opts.capacity, n_tiles)
+    b = bins.cpu().numpy()
+    k, _ = read_status(bins)
+    k = min(k, opts.capacity)
+    bits = 32 + max(1, int(np.ceil(np.log2(max(n_tiles, 2)))))
+    parity = ((bits + 7) // 8) & 1
+    keys = b[L["keys1" if parity else "keys0"]:][: 8 * k].view(np.uint64)
+    vals = b[L["vals1" if parity else "vals0"]:][: 4 * k].view(np.uint32)
+    gid = b[L["gid"]:][: 4 * opts.capacity].view(np.int32)
+    ids = gid[vals]
+    ranges = b[L["ranges"]:][: 8 * n_tiles].view(np.int32).reshape(n_tiles, 2)
+    return keys, ids, ranges
+
+
+def proj_view(proj: torch.Tensor, n, n_cams):
+    """Debug view of sof_project's per (camera, Gaussian) records as numpy arrays
+    (synchronises): rect [V*N,4] int16, mu_z [V*N] float32, zmin [V*N] float32."""
+    vn = n * n_cams
+    o, L = 0, {}
+    for name, size in [("geom", vn * 64), ("app", vn * 32), ("bwdr", vn * 32), ("rect", vn * 8), ("zmin", vn * 4)]:
+        L[name] = o
+        o = _align(o + size)
+    b = proj.cpu().numpy()
+    geom = b[L["geom"]:L["geom"] + vn * 64].view(np.float32).reshape(vn, 16)
+    rect = b[L["rect"]:L["rect"] + vn * 8].view(np.int16).reshape(vn, 4)
+    zmin = b[L["zmin"]:L["zmin"] + vn * 4].view(np.float32)
+    app = b[L["app"]:L["app"] + vn * 32].view(np.float32).reshape(vn, 8)
+    return dict(rect=rect.copy(), mu_z=geom[:, 12].copy(), zmin=zmin.copy(), color=app[:, :3].copy(),
+                normal=app[:, 4:7].copy(), geom=geom.copy())
+
+
+def _align(x, a=256):
+    return (x + a - 1) // a * a
+
+
+def _bins_layout(vn, n_cams, cap, n_tiles):
+    """Python mirror of the BinsLayout offsets (for debug views only)."""
+    sort_tile, scan_chunk = 8 * 256, 16 * 256
+    nb = -(-max(cap, 1) // sort_tile)
+    L, o = {}, 0
+    for name, size in [("status", 256), ("cams", (n_cams + 1) * 32), ("counts", vn * 4), ("offsets", vn * 8),
+                       ("scan_tmp", (-(-max(vn, 1) // scan_chunk) + 1) * 8), ("keys0", cap * 8), ("keys1", cap * 8),
+                       ("vals0", cap * 4), ("vals1", cap * 4), ("gid", cap * 4), ("hist", 256 * nb * 4),
+                       ("hist_tmp", (-(-(256 * nb) // scan_chunk) + 1) * 8), ("ranges", max(n_tiles, 1) * 8)]:
+        L[name] = o
+        o = _align(o + size)
+    L["total"] = o
+    return L
+
+
+# ------------------------------------------------------------------------------ high level
+
+class Rasterizer:
+    """Owns the three workspace buffers for one camera set and grows the instance capacity
+    on demand (the only host read-back happens when `auto_capacity` is on)."""
+
+    def __init__(self, cams: Cameras, opts: Options, auto_capacity=True, device="cuda"):
+        self.cams, self.opts, self.device = cams, opts, device
+        self.auto_capacity = auto_capacity
+        self.proj = self.bins = self.grads = None
+        self._n = -1
+        self.last_count = 0
+
+    def _alloc(self, n):
+        p, b, g = workspace_size(n, self.cams, self.opts)
+        if self.proj is None or self.proj.numel() < p:
+            self.proj = torch.empty(p, dtype=torch.uint8, device=self.device)
+        if self.bins is None or self.bins.numel() < b:
+            self.bins = torch.empty(b, dtype=torch.uint8, device=self.device)
+        if self.grads is None or self.grads.numel() < g:
+            self.grads = torch.empty(max(g, 16), dtype=torch.uint8, device=self.device)
+
+    def prepare(self, g: Gaussians):
+        """project + bin_sort; returns the instance count (read back only in auto mode)."""
+        n = g.n
+        if self.opts.capacity <= 0:
+            self.opts.capacity = max(1024, 4 * n * len(self.cams))
+        self._alloc(n)
+        project(g, self.cams, self.opts, self.proj)
+        bin_sort(n, self.cams, self.opts, self.proj, self.bins)
+        if self.auto_capacity:
+            k, flags = read_status(self.bins)
+            self.last_count = k
+            if k > self.opts.capacity:
+                self.opts.capacity = int(k * 1.25) + 1024
+                self._alloc(n)
+                bin_sort(n, self.cams, self.opts, self.proj, self.bins)
+        return self.last_count
+
+    def alloc_outputs(self):
+        P = self.cams.n_pixels
+        dev = self.device
+        return dict(rgb=torch.empty(3 * P, device=dev), acc=torch.empty(P, device=dev), depth=torch.empty(P, device=dev),
+                    normal=torch.empty(3 * P, device=dev), aux=torch.empty(4 * P, device=dev))
+
+    def forward(self, g: Gaussians, out=None):
+        self.prepare(g)
+        out = out or self.alloc_outputs()
+        render_fwd(g.n, self.cams, self.opts, self.proj, self.bins, out["rgb"], out["acc"], out["depth"],
+                   out["normal"], out["aux"])
+        return out
+
+    def backward(self, g: Gaussians, out, d_rgb=None, d_acc=None, d_depth=None, d_normal=None, grads_out=None):
+        if grads_out is None:
+            grads_out = dict(means=torch.empty_like(g.means), scales=torch.empty_like(g.scales),
+                             quats=torch.empty_like(g.quats), opac=torch.empty_like(g.opac),
+                             sh=torch.empty_like(g.sh))
+        render_bwd(g, self.cams, self.opts, self.proj, self.bins, out["rgb"], out["normal"], out["aux"], d_rgb, d_acc,
+                   d_depth, d_normal, self.grads, grads_out["means"], grads_out["scales"], grads_out["quats"],
+                   grads_out["opac"], grads_out["sh"])
+        return grads_out
+
+    def split(self, flat, channels):
+        """Split a concatenated output into per-camera [C,H,W] views."""
+        res, off = [], 0
+        for w, h in self.cams.sizes:
+            res.append(flat[off:off + channels * w * h].view(channels, h, w))
+            off += channels * w * h
+        return res
+
+
+class SofRasterize(torch.autograd.Function):
+    """Differentiable render of activated Gaussian parameters.
+
+    forward(means, scales, quats, opac, sh, rasterizer) -> (rgb, acc, depth, normal), each the
+    concatenation over the rasterizer's cameras ([3*P], [P], [P], [3*P])."""
+
+    @staticmethod
+    def forward(ctx, means, scales, quats, opac, sh, rast: Rasterizer, sh_degree: int):
+        g = Gaussians(means.contiguous(), scales.contiguous(), quats.contiguous(), opac.contiguous(),
+                      sh.contiguous(), int(sh_degree))
+        out = rast.forward(g)
+        ctx.rast, ctx.g, ctx.out = rast, g, out
+        return out["rgb"], out["acc"], out["depth"], out["normal"]
+
+    @staticmethod
+    def backward(ctx, d_rgb, d_acc, d_depth, d_normal):
+        c = lambda t: None if t is None else t.contiguous()
+        gr = ctx.rast.backward(ctx.g, ctx.out, c(d_rgb), c(d_acc), c(d_depth), c(d_normal))
+        return gr["means"], gr["scales"], gr["quats"], gr["opac"], gr["sh"], None, None
