@@ -155,8 +155,9 @@ int sof_bin_sort(int64_t n, const sof_camera* h_cams, const sof_camera* d_cams, 
  *                               T_k > 1/2 >= T_k (1 - alpha_k); 0 without a crossing
  *                               (t*_k with SOF_DEPTH_MEDIAN)
  *   normal [3,H,W]              sum w n (not normalised)
- *   aux    [4,H,W] float32 bits T_end, n_emitted (int32), k (int32 Gaussian index or -1),
- *                               T_k -- needed by sof_render_bwd.
+ *   aux    [6,H,W] float32 bits T_end, n_emitted (int32), k (int32 Gaussian index or -1),
+ *                               T_k -- needed by sof_render_bwd -- then two int32 work
+ *                               counters: list entries tested and candidates found.
  */
 int sof_render_fwd(int64_t n, const sof_camera* h_cams, const sof_camera* d_cams, int32_t n_cams,
                    const sof_options* opts, const void* proj, size_t proj_bytes, const void* bins,

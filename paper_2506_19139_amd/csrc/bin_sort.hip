@@ -289,10 +289,16 @@ __global__ __launch_bounds__(256) void k_ranges(const uint64_t* keys, const int6
   if (i == n - 1 || (uint32_t)(keys[i + 1] >> 32) != t) ranges[t].y = (int)(i + 1);
 }
 
+hipError_t launch_cam_table(const sof_camera* d_cams, int n_cams, int tile, CamInfo* out, StatusBlock* status,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_cam_table, dim3(1), dim3(64), 0, s, d_cams, n_cams, tile, out, status);
+  return hipGetLastError();
+}
+
 hipError_t launch_bin_sort(int64_t n, const sof_camera* d_cams, int n_cams, int64_t n_tiles, int tile, int64_t cap,
                            int query_keys, const void* proj, void* bins, hipStream_t s, int* parity) {
   const int64_t vn = n * (int64_t)n_cams;
-  const ProjLayout P = ProjLayout::make(vn);
+  const ProjLayout P = ProjLayout::make(vn, query_keys != 0, n);
   const BinsLayout B = BinsLayout::make(vn, n_cams, cap, n_tiles);
   const char* pb = (const char*)proj;
   char* bb = (char*)bins;

@@ -13,11 +13,14 @@ hipError_t radix_sort(K* k0, uint32_t* v0, K* k1, uint32_t* v1, const int64_t* c
                       int32_t* hist, int32_t* hist_tmp, int* out_parity, hipStream_t s);
 
 hipError_t launch_project(const sof_gaussians* g, const sof_camera* d_cams, int n_cams, float near_plane,
-                          void* proj, hipStream_t stream);
+                          void* proj, hipStream_t stream, bool query = false);
 
 // parity: which of the two key/value buffers holds the sorted instances (0 or 1).
 hipError_t launch_bin_sort(int64_t n, const sof_camera* d_cams, int n_cams, int64_t n_tiles, int tile, int64_t cap,
                            int query_keys, const void* proj, void* bins, hipStream_t s, int* parity);
+// Per-camera tile / pixel offsets on the device (also resets the status block).
+hipError_t launch_cam_table(const sof_camera* d_cams, int n_cams, int tile, CamInfo* out, StatusBlock* status,
+                            hipStream_t s);
 
 struct RenderFwdArgs {
   int64_t n;

@@ -26,6 +26,8 @@ struct ProjectArgs {
   float4* bwdr;
   short4* rect;
   float* zmin;
+  float4* world;      // query layout only (else null): per-Gaussian S^-1 R^T rows and mean
+  int query;          // 1: skip colour / normal / backward records
 };
 
 __device__ inline int clamp_floor(double v) {
@@ -157,6 +159,7 @@ __global__ __launch_bounds__(256) void k_project(ProjectArgs a) {
   a.geom[4 * idx + 1] = r1;
   a.geom[4 * idx + 2] = r2;
   a.geom[4 * idx + 3] = r3;
+  if (a.query) return;
   a.bwdr[2 * idx + 0] = make_float4((float)P[0], (float)P[1], (float)P[2], (float)P[3]);
   a.bwdr[2 * idx + 1] = make_float4((float)P[4], (float)P[5], (float)dmx, (float)dmy);
 
@@ -184,11 +187,27 @@ __global__ __launch_bounds__(256) void k_project(ProjectArgs a) {
   a.app[2 * idx + 1] = make_float4((float)nx, (float)ny, (float)nz, 0.f);
 }
 
+// World record for point queries: row k of S^-1 R^T is (column k of R) / s_k.
+__global__ __launch_bounds__(256) void k_world(const float* means, const float* scales, const float* quats, int64_t n,
+                                               float4* world) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double qw = quats[4 * i], qx = quats[4 * i + 1], qy = quats[4 * i + 2], qz = quats[4 * i + 3];
+  const double qn = rsqrt(qw * qw + qx * qx + qy * qy + qz * qz);
+  double R[9];
+  quat_rot<double>(qw * qn, qx * qn, qy * qn, qz * qn, R);
+  const double is0 = 1.0 / scales[3 * i], is1 = 1.0 / scales[3 * i + 1], is2 = 1.0 / scales[3 * i + 2];
+  world[4 * i + 0] = make_float4((float)(R[0] * is0), (float)(R[3] * is0), (float)(R[6] * is0), (float)(R[1] * is1));
+  world[4 * i + 1] = make_float4((float)(R[4] * is1), (float)(R[7] * is1), (float)(R[2] * is2), (float)(R[5] * is2));
+  world[4 * i + 2] = make_float4((float)(R[8] * is2), means[3 * i], means[3 * i + 1], means[3 * i + 2]);
+  world[4 * i + 3] = make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
 hipError_t launch_project(const sof_gaussians* g, const sof_camera* d_cams, int n_cams, float near_plane,
-                          void* proj, hipStream_t stream) {
+                          void* proj, hipStream_t stream, bool query) {
   const int64_t vn = g->n * (int64_t)n_cams;
   if (vn == 0) return hipSuccess;
-  ProjLayout L = ProjLayout::make(vn);
+  ProjLayout L = ProjLayout::make(vn, query, g->n);
   char* base = (char*)proj;
   ProjectArgs a;
   a.means = g->means; a.scales = g->scales; a.quats = g->quats; a.opac = g->opacities; a.sh = g->sh;
@@ -198,9 +217,14 @@ hipError_t launch_project(const sof_gaussians* g, const sof_camera* d_cams, int 
   a.bwdr = (float4*)(base + L.bwdr);
   a.rect = (short4*)(base + L.rect);
   a.zmin = (float*)(base + L.zmin);
+  a.world = query ? (float4*)(base + L.world) : nullptr;
+  a.query = query ? 1 : 0;
   const int threads = 256;
   const int64_t blocks = div_up(vn, threads);
   hipLaunchKernelGGL(k_project, dim3((unsigned)blocks), dim3(threads), 0, stream, a);
+  if (query)
+    hipLaunchKernelGGL(k_world, dim3((unsigned)div_up(g->n, threads)), dim3(threads), 0, stream, g->means, g->scales,
+                       g->quats, g->n, a.world);
   return hipGetLastError();
 }
 

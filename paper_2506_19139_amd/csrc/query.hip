@@ -1,6 +1,403 @@
-// placeholder, replaced below
-#include "launch.h"
-extern "C" {
-int sof_query_workspace_size(int64_t, const sof_camera*, int32_t, const sof_options*, int64_t, int64_t, size_t*, size_t*, size_t*) { return SOF_E_UNSUPPORTED; }
-int sof_opacity_query(const sof_gaussians*, const sof_camera*, const sof_camera*, int32_t, const sof_options*, const float*, int64_t, int64_t, float*, void*, size_t, void*, size_t, void*, size_t, hipStream_t) { return SOF_E_UNSUPPORTED; }
+// Opacity-field queries (Eq. (12)-(13)) at arbitrary points over many views, with the
+// paper's ray/tile scheduling of points (Sec. 3.4, Eq. (14)) and z_min early stopping
+// (Eq. (15)).
+//
+// Pipeline (all on the device, one persistent evaluation launch for every view):
+//   1. project all (view, Gaussian) pairs; per-Gaussian world record S^-1 R^T, mean;
+//   2. per (view, tile) Gaussian lists sorted by z_min (the same stable radix sort);
+//   3. every (point, view) pair that sees the point gets the key [view tile, depth]
+//      (depth log-quantised: the order only balances work) and is radix-sorted;
+//   4. per tile ceil(N_P / 256) blocks of 256 points, an inclusive scan and a block -> tile
+//      lookup table;
+//   5. a persistent kernel pulls blocks from an atomic counter; the 256 lanes share the
+//      tile's Gaussian list staged through LDS and each lane accumulates
+//      T = prod (1 - alpha_i(t_eval)) for its point, stopping at z_min > z(x) or once
+//      1 - T reaches the point's running minimum over views (the min cannot drop then);
+//      the result enters the output through an atomic min on the float bits (values are
+//      non-negative, so their bit patterns order like the floats).
+// Order independence of O_N (App. A.2) is what allows walking lists in z_min order.
+#include "render_common.h"
+
+namespace sof {
+
+constexpr int kQueryBlock = 256;
+
+// sched buffer layout.
+struct SchedLayout {
+  size_t status, cnt, off, scan_tmp, keys0, keys1, vals0, vals1, hist, hist_tmp, pranges, nblk, blk_off, blk_tmp, lut,
+      total;
+  int64_t pvcap, max_blocks;
+  static __host__ __device__ SchedLayout make(int64_t n_points, int64_t pvcap, int64_t n_tiles) {
+    SchedLayout L;
+    L.pvcap = pvcap;
+    L.max_blocks = div_up(pvcap, kQueryBlock) + n_tiles + 1;
+    const int64_t nb = div_up(pvcap > 0 ? pvcap : 1, kSortTile);
+    size_t o = 0;
+    L.status = o;   o = align_up(o + sizeof(StatusBlock));
+    L.cnt = o;      o = align_up(o + (size_t)n_points * 4);
+    L.off = o;      o = align_up(o + (size_t)n_points * 8);
+    L.scan_tmp = o; o = align_up(o + (size_t)(div_up(n_points > 0 ? n_points : 1, kScanChunk) + 1) * 8);
+    L.keys0 = o;    o = align_up(o + (size_t)pvcap * 4);
+    L.keys1 = o;    o = align_up(o + (size_t)pvcap * 4);
+    L.vals0 = o;    o = align_up(o + (size_t)pvcap * 4);
+    L.vals1 = o;    o = align_up(o + (size_t)pvcap * 4);
+    L.hist = o;     o = align_up(o + (size_t)256 * nb * 4);
+    L.hist_tmp = o; o = align_up(o + (size_t)(div_up(256 * nb, kScanChunk) + 1) * 8);
+    L.pranges = o;  o = align_up(o + (size_t)(n_tiles > 0 ? n_tiles : 1) * 8);
+    L.nblk = o;     o = align_up(o + (size_t)(n_tiles > 0 ? n_tiles : 1) * 4);
+    L.blk_off = o;  o = align_up(o + (size_t)(n_tiles > 0 ? n_tiles : 1) * 4);
+    L.blk_tmp = o;  o = align_up(o + (size_t)(div_up(n_tiles > 0 ? n_tiles : 1, kScanChunk) + 1) * 8);
+    L.lut = o;      o = align_up(o + (size_t)L.max_blocks * 4);
+    L.total = o;
+    return L;
+  }
+};
+
+// Projection of a point into a view in float64; true when the view sees it.
+__device__ inline bool view_point(const sof_camera& cam, float near_plane, float x, float y, float z, double& u,
+                                  double& v, double& zc) {
+  const double xc = (double)cam.R[0] * x + (double)cam.R[1] * y + (double)cam.R[2] * z + cam.t[0];
+  const double yc = (double)cam.R[3] * x + (double)cam.R[4] * y + (double)cam.R[5] * z + cam.t[1];
+  zc = (double)cam.R[6] * x + (double)cam.R[7] * y + (double)cam.R[8] * z + cam.t[2];
+  if (!(zc > (double)near_plane)) return false;
+  u = cam.fx * xc / zc + cam.cx;
+  v = cam.fy * yc / zc + cam.cy;
+  return u >= 0.0 && u < (double)cam.width && v >= 0.0 && v < (double)cam.height;
 }
+
+__global__ __launch_bounds__(256) void k_pv_count(const float* pts, int64_t np, const sof_camera* cams, int n_cams,
+                                                  float near_plane, int32_t* cnt) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= np) return;
+  const float x = pts[3 * p], y = pts[3 * p + 1], z = pts[3 * p + 2];
+  int c = 0;
+  for (int v = 0; v < n_cams; ++v) {
+    double u, w, zc;
+    c += view_point(cams[v], near_plane, x, y, z, u, w, zc) ? 1 : 0;
+  }
+  cnt[p] = c;
+}
+
+__device__ inline uint32_t quantised_depth(double z, float near_plane, int bits) {
+  // log-spaced over [near, near * 2^20]; only used to order points inside a tile
+  const double l = log2(z / (double)near_plane) * (1.0 / 20.0);
+  const double m = (double)((1u << bits) - 1u);
+  const double q = l <= 0.0 ? 0.0 : (l >= 1.0 ? m : l * m);
+  return (uint32_t)q;
+}
+
+__global__ __launch_bounds__(256) void k_pv_emit(const float* pts, int64_t np, const sof_camera* cams,
+                                                 const CamInfo* ci, int n_cams, float near_plane, int tile,
+                                                 const int32_t* cnt, const int64_t* off, int64_t pvcap, int dbits,
+                                                 uint32_t* keys, uint32_t* vals, StatusBlock* status) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= np) return;
+  const int c = cnt[p];
+  if (c == 0) return;
+  int64_t e = off[p];
+  if (e + c > pvcap) atomicOr(&status->flags, 1);
+  const float x = pts[3 * p], y = pts[3 * p + 1], z = pts[3 * p + 2];
+  for (int v = 0; v < n_cams; ++v) {
+    double u, w, zc;
+    if (!view_point(cams[v], near_plane, x, y, z, u, w, zc)) continue;
+    if (e >= pvcap) return;
+    const uint32_t t = (uint32_t)(ci[v].tile_off + ((int)w / tile) * ci[v].tiles_x + ((int)u / tile));
+    keys[e] = (t << dbits) | quantised_depth(zc, near_plane, dbits);
+    vals[e] = (uint32_t)p;
+    ++e;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_zero_i32(int32_t* a, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = 0;
+}
+
+__global__ __launch_bounds__(256) void k_fill_f32(float* a, int64_t n, float v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = v;
+}
+
+__global__ __launch_bounds__(256) void k_pv_ranges(const uint32_t* keys, const int64_t* count, int64_t cap, int dbits,
+                                                   int2* ranges) {
+  const int64_t k = *count;
+  const int64_t n = k < cap ? k : cap;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t t = keys[i] >> dbits;
+  if (i == 0 || (keys[i - 1] >> dbits) != t) ranges[t].x = (int)i;
+  if (i == n - 1 || (keys[i + 1] >> dbits) != t) ranges[t].y = (int)(i + 1);
+}
+
+__global__ __launch_bounds__(256) void k_nblk(const int2* ranges, int64_t n_tiles, int32_t* nblk) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_tiles) return;
+  const int2 r = ranges[t];
+  nblk[t] = (r.y - r.x + kQueryBlock - 1) / kQueryBlock;
+}
+
+__global__ __launch_bounds__(256) void k_lut(const int32_t* nblk, const int32_t* blk_off, int64_t n_tiles,
+                                             int64_t max_blocks, int32_t* lut) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_tiles) return;
+  const int b0 = blk_off[t];
+  for (int k = 0; k < nblk[t]; ++k)
+    if (b0 + k < max_blocks) lut[b0 + k] = (int32_t)t;
+}
+
+struct __align__(16) StageQ {
+  int ui, vi;
+  float uf, vf;
+  float gx, gy, cxx, cxy2;
+  float cyy, mxx, mxy2, myy;
+  float mz, o, thr, zmin;
+  float m[9];
+  float mu[3];
+};
+
+struct QueryArgs {
+  const float* pts;
+  const sof_camera* cams;
+  const CamInfo* cam_info;
+  int n_cams;
+  float near_plane;
+  int64_t n;
+  const float4* geom;
+  const float* zmin;
+  const float4* world;
+  const int2* granges;          // Gaussian tile lists
+  const uint32_t* gvals;
+  const int32_t* ggid;
+  const int2* pranges;          // point lists per tile
+  const uint32_t* pvals;
+  const int32_t* blk_off;
+  const int32_t* lut;
+  const int64_t* total_blocks;
+  int32_t* counter;
+  float* out;
+};
+
+__global__ __launch_bounds__(kQueryBlock) void k_query_eval(QueryArgs a) {
+  __shared__ StageQ stage[kQueryBlock];
+  __shared__ int s_blk;
+  const int64_t total = *a.total_blocks;
+  for (;;) {
+    __syncthreads();
+    if (threadIdx.x == 0) s_blk = atomicAdd(a.counter, 1);
+    __syncthreads();
+    const int b = s_blk;
+    if (b >= total) break;
+    const int t = a.lut[b];
+    const int2 pr = a.pranges[t];
+    const int i = pr.x + (b - a.blk_off[t]) * kQueryBlock + (int)threadIdx.x;
+    const bool active = i < pr.y;
+    const int c = find_cam(a.cam_info, a.n_cams, t);
+    const sof_camera& cam = a.cams[c];
+    const int64_t cam_base = (int64_t)c * a.n;
+
+    uint32_t p = 0;
+    float px = 0.f, py = 0.f, pz = 0.f, zx = 0.f, uxf = 0.f, vyf = 0.f, cur = 1.f;
+    int uxi = 0, vyi = 0;
+    bool done = !active;
+    if (active) {
+      p = a.pvals[i];
+      px = a.pts[3 * p]; py = a.pts[3 * p + 1]; pz = a.pts[3 * p + 2];
+      double u, v, zc;
+      view_point(cam, a.near_plane, px, py, pz, u, v, zc);
+      const double fu = floor(u), fv = floor(v);
+      uxi = (int)fu; vyi = (int)fv;
+      uxf = (float)(u - fu); vyf = (float)(v - fv);
+      zx = (float)zc;
+      cur = a.out[p];
+    }
+    float T = 1.f;
+    bool pruned = false;
+    const int2 gr = a.granges[t];
+    for (int gs = gr.x; gs < gr.y; gs += kQueryBlock) {
+      if (__syncthreads_count(!done) == 0) break;
+      const int gi = gs + (int)threadIdx.x;
+      if (gi < gr.y) {
+        const int32_t g = a.ggid[a.gvals[gi]];
+        const int64_t vg = cam_base + g;
+        const float4 r0 = a.geom[4 * vg], r1 = a.geom[4 * vg + 1], r2 = a.geom[4 * vg + 2], r3 = a.geom[4 * vg + 3];
+        const float4 w0 = a.world[4 * g], w1 = a.world[4 * g + 1], w2 = a.world[4 * g + 2];
+        StageQ e;
+        e.ui = __float_as_int(r0.x); e.uf = r0.y; e.vi = __float_as_int(r0.z); e.vf = r0.w;
+        e.gx = r1.x; e.gy = r1.y; e.cxx = r1.z; e.cxy2 = r1.w;
+        e.cyy = r2.x; e.mxx = r2.y; e.mxy2 = r2.z; e.myy = r2.w;
+        e.mz = r3.x; e.o = r3.y; e.thr = r3.z; e.zmin = a.zmin[vg];
+        e.m[0] = w0.x; e.m[1] = w0.y; e.m[2] = w0.z; e.m[3] = w0.w;
+        e.m[4] = w1.x; e.m[5] = w1.y; e.m[6] = w1.z; e.m[7] = w1.w;
+        e.m[8] = w2.x; e.mu[0] = w2.y; e.mu[1] = w2.z; e.mu[2] = w2.w;
+        stage[threadIdx.x] = e;
+      }
+      __syncthreads();
+      const int nb = min(kQueryBlock, gr.y - gs);
+      if (!done) {
+        for (int j = 0; j < nb; ++j) {
+          const StageQ& e = stage[j];
+          if (e.zmin > zx) { done = true; break; }
+          const float dx = (float)(uxi - e.ui) + (uxf - e.uf);
+          const float dy = (float)(vyi - e.vi) + (vyf - e.vf);
+          const Quad q = quad_terms(e.gx, e.gy, e.cxx, e.cxy2, e.cyy, e.mxx, e.mxy2, e.myy, dx, dy);
+          if (!(q.den > 0.f)) continue;
+          if (q.num > 1.0001f * e.thr * q.den) continue;       // q* already beyond the cutoff
+          const float sn = e.mz * (1.f + q.b);
+          float xk;
+          if (sn < zx * q.den) {                                 // peak in front of the point
+            if (!(sn > a.near_plane * q.den)) continue;
+            xk = fmaxf(q.num / q.den, 0.f);
+          } else {                                               // evaluate at the point itself
+            const float wx = px - e.mu[0], wy = py - e.mu[1], wz = pz - e.mu[2];
+            const float g0 = fmaf(e.m[0], wx, fmaf(e.m[1], wy, e.m[2] * wz));
+            const float g1 = fmaf(e.m[3], wx, fmaf(e.m[4], wy, e.m[5] * wz));
+            const float g2 = fmaf(e.m[6], wx, fmaf(e.m[7], wy, e.m[8] * wz));
+            xk = kHalfLog2e * fmaf(g0, g0, fmaf(g1, g1, g2 * g2));
+          }
+          const float al = fminf(kAlphaMax, e.o * exp2f(-xk));
+          if (al < kAlphaMin) continue;
+          T *= 1.f - al;
+          if (1.f - T >= cur) { done = true; pruned = true; break; }
+        }
+      }
+    }
+    if (active && !pruned) atomicMin((unsigned int*)(a.out + p), __float_as_uint(1.f - T));
+  }
+}
+
+}  // namespace sof
+
+using namespace sof;
+
+extern "C" {
+
+int sof_query_workspace_size(int64_t n, const sof_camera* h_cams, int32_t n_cams, const sof_options* opts,
+                             int64_t n_points, int64_t pv_capacity, size_t* proj_bytes, size_t* bins_bytes,
+                             size_t* sched_bytes) {
+  if (!opts || !h_cams || n_cams < 1 || n < 0 || n >= (int64_t(1) << 31)) return SOF_E_ARG;
+  if (opts->tile != 8 && opts->tile != 16 && opts->tile != 32) return SOF_E_ARG;
+  if (opts->capacity < 0 || opts->capacity >= (int64_t(1) << 31)) return SOF_E_ARG;
+  if (n_points < 0 || n_points >= (int64_t(1) << 31) || pv_capacity < 0 || pv_capacity >= (int64_t(1) << 31))
+    return SOF_E_ARG;
+  int64_t n_tiles = 0;
+  for (int c = 0; c < n_cams; ++c) {
+    if (h_cams[c].width < 1 || h_cams[c].height < 1 || h_cams[c].width > 32767 || h_cams[c].height > 32767)
+      return SOF_E_ARG;
+    n_tiles += (int64_t)((h_cams[c].width + opts->tile - 1) / opts->tile) * ((h_cams[c].height + opts->tile - 1) / opts->tile);
+  }
+  if (bits_for(n_tiles) > 24) return SOF_E_UNSUPPORTED;
+  const int64_t vn = n * n_cams;
+  if (proj_bytes) *proj_bytes = ProjLayout::make(vn, true, n).total;
+  if (bins_bytes) *bins_bytes = BinsLayout::make(vn, n_cams, opts->capacity, n_tiles).total;
+  if (sched_bytes) *sched_bytes = SchedLayout::make(n_points, pv_capacity, n_tiles).total;
+  return SOF_OK;
+}
+
+int sof_opacity_query(const sof_gaussians* g, const sof_camera* h_cams, const sof_camera* d_cams, int32_t n_cams,
+                      const sof_options* opts, const float* points, int64_t n_points, int64_t pv_capacity,
+                      float* opacity, void* proj, size_t proj_bytes, void* bins, size_t bins_bytes, void* sched,
+                      size_t sched_bytes, hipStream_t s) {
+  size_t pb = 0, bb = 0, sb = 0;
+  int st = sof_query_workspace_size(g ? g->n : -1, h_cams, n_cams, opts, n_points, pv_capacity, &pb, &bb, &sb);
+  if (st) return st;
+  if (g->sh_degree < 0 || g->sh_degree > 3) return SOF_E_ARG;
+  if (g->n > 0 && (!g->means || !g->scales || !g->quats || !g->opacities || !g->sh)) return SOF_E_ARG;
+  if (!d_cams || !bins || !sched || (n_points > 0 && (!points || !opacity)) || (!proj && g->n > 0)) return SOF_E_ARG;
+  if (proj_bytes < pb || bins_bytes < bb || sched_bytes < sb) return SOF_E_WORKSPACE;
+  if (!(opts->near_plane > 0.f)) return SOF_E_ARG;
+  int64_t n_tiles = 0;
+  for (int c = 0; c < n_cams; ++c)
+    n_tiles += (int64_t)((h_cams[c].width + opts->tile - 1) / opts->tile) * ((h_cams[c].height + opts->tile - 1) / opts->tile);
+  const int tile = opts->tile;
+  const float near_plane = opts->near_plane;
+  const int64_t n = g->n, vn = n * n_cams;
+  const int th = 256;
+  hipError_t e = hipSuccess;
+
+  // 1-2: Gaussians -> per (view, tile) lists sorted by z_min
+  if ((e = launch_project(g, d_cams, n_cams, near_plane, proj, s, true)) != hipSuccess) return SOF_E_HIP;
+  int gpar = 0;
+  if ((e = launch_bin_sort(n, d_cams, n_cams, n_tiles, tile, opts->capacity, 1, proj, bins, s, &gpar)) != hipSuccess)
+    return SOF_E_HIP;
+  const ProjLayout P = ProjLayout::make(vn, true, n);
+  const BinsLayout B = BinsLayout::make(vn, n_cams, opts->capacity, n_tiles);
+  char* pbase = (char*)proj;
+  char* bbase = (char*)bins;
+  char* sbase = (char*)sched;
+  const SchedLayout S = SchedLayout::make(n_points, pv_capacity, n_tiles);
+  StatusBlock* sst = (StatusBlock*)(sbase + S.status);
+  const CamInfo* ci = (const CamInfo*)(bbase + B.cams);
+
+  // 3: (point, view) pairs keyed by [view tile, depth]
+  // reset the schedule's status block (count, flags, block total, work counter)
+  hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(th), 0, s, (int32_t*)sst, (int64_t)(sizeof(StatusBlock) / 4));
+  int32_t* cnt = (int32_t*)(sbase + S.cnt);
+  int64_t* off = (int64_t*)(sbase + S.off);
+  if (n_points > 0)
+    hipLaunchKernelGGL(k_pv_count, dim3((unsigned)div_up(n_points, th)), dim3(th), 0, s, points, n_points, d_cams,
+                       n_cams, near_plane, cnt);
+  if ((e = exclusive_scan<int32_t, int64_t>(cnt, n_points, off, (int64_t*)(sbase + S.scan_tmp), &sst->count, s)) !=
+      hipSuccess)
+    return SOF_E_HIP;
+  const int tbits = bits_for(n_tiles);
+  const int dbits = 32 - tbits;
+  uint32_t* k0 = (uint32_t*)(sbase + S.keys0);
+  uint32_t* k1 = (uint32_t*)(sbase + S.keys1);
+  uint32_t* v0 = (uint32_t*)(sbase + S.vals0);
+  uint32_t* v1 = (uint32_t*)(sbase + S.vals1);
+  if (n_points > 0)
+    hipLaunchKernelGGL(k_pv_emit, dim3((unsigned)div_up(n_points, th)), dim3(th), 0, s, points, n_points, d_cams, ci,
+                       n_cams, near_plane, tile, cnt, off, pv_capacity, dbits, k0, v0, sst);
+  int ppar = 0;
+  if ((e = radix_sort<uint32_t>(k0, v0, k1, v1, &sst->count, pv_capacity, 32, (int32_t*)(sbase + S.hist),
+                                (int32_t*)(sbase + S.hist_tmp), &ppar, s)) != hipSuccess)
+    return SOF_E_HIP;
+  const uint32_t* pk = ppar ? k1 : k0;
+  const uint32_t* pv = ppar ? v1 : v0;
+
+  // 4: blocks of 256 points per tile, scan, block -> tile table
+  int2* pranges = (int2*)(sbase + S.pranges);
+  int32_t* nblk = (int32_t*)(sbase + S.nblk);
+  int32_t* blk_off = (int32_t*)(sbase + S.blk_off);
+  int32_t* lut = (int32_t*)(sbase + S.lut);
+  hipLaunchKernelGGL(k_zero_i32, dim3((unsigned)div_up(2 * n_tiles, th)), dim3(th), 0, s, (int32_t*)pranges,
+                     2 * n_tiles);
+  if (pv_capacity > 0)
+    hipLaunchKernelGGL(k_pv_ranges, dim3((unsigned)div_up(pv_capacity, th)), dim3(th), 0, s, pk, &sst->count,
+                       pv_capacity, dbits, pranges);
+  hipLaunchKernelGGL(k_nblk, dim3((unsigned)div_up(n_tiles, th)), dim3(th), 0, s, pranges, n_tiles, nblk);
+  if ((e = exclusive_scan<int32_t, int32_t>(nblk, n_tiles, blk_off, (int32_t*)(sbase + S.blk_tmp), &sst->aux[0], s)) !=
+      hipSuccess)
+    return SOF_E_HIP;
+  hipLaunchKernelGGL(k_lut, dim3((unsigned)div_up(n_tiles, th)), dim3(th), 0, s, nblk, blk_off, n_tiles, S.max_blocks,
+                     lut);
+  if (n_points > 0)
+    hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)div_up(n_points, th)), dim3(th), 0, s, opacity, n_points, 1.0f);
+
+  // 5: persistent evaluation over every (view, tile, block)
+  QueryArgs qa;
+  qa.pts = points; qa.cams = d_cams; qa.cam_info = ci; qa.n_cams = n_cams; qa.near_plane = near_plane; qa.n = n;
+  qa.geom = (const float4*)(pbase + P.geom);
+  qa.zmin = (const float*)(pbase + P.zmin);
+  qa.world = (const float4*)(pbase + P.world);
+  qa.granges = (const int2*)(bbase + B.ranges);
+  qa.gvals = (const uint32_t*)(bbase + (gpar ? B.vals1 : B.vals0));
+  qa.ggid = (const int32_t*)(bbase + B.gid);
+  qa.pranges = pranges;
+  qa.pvals = pv;
+  qa.blk_off = blk_off;
+  qa.lut = lut;
+  qa.total_blocks = &sst->aux[0];
+  qa.counter = (int32_t*)&sst->aux[1];
+  qa.out = opacity;
+  int dev = 0, cus = 0, per_cu = 0;
+  hipGetDevice(&dev);
+  hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_query_eval, kQueryBlock, 0);
+  const int64_t grid = (int64_t)(cus > 0 ? cus : 256) * (per_cu > 0 ? per_cu : 1);
+  const int64_t maxb = S.max_blocks;
+  hipLaunchKernelGGL(k_query_eval, dim3((unsigned)(grid < maxb ? grid : maxb)), dim3(kQueryBlock), 0, s, qa);
+  return hipGetLastError() == hipSuccess ? SOF_OK : SOF_E_HIP;
+}
+
+}  // extern "C"

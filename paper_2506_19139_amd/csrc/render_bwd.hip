@@ -63,7 +63,7 @@ __global__ __launch_bounds__(TS * TS) void k_render_bwd(RenderBwdArgs A) {
   float fr = 0, fg = 0, fb = 0, fnx = 0, fny = 0, fnz = 0;
   float gr = 0, gg = 0, gb = 0, ga = 0, gd = 0, gnx = 0, gny = 0, gnz = 0;
   if (inside) {
-    const float* aux = a.aux + 4 * ci.pix_off;
+    const float* aux = a.aux + kAuxChannels * ci.pix_off;
     T_end = aux[pix];
     n_emit = __float_as_int(aux[hw + pix]);
     kgid = __float_as_int(aux[2 * hw + pix]);

@@ -3,15 +3,16 @@
 // 64-byte record load per lane; every lane then walks the batch from LDS (broadcast reads),
 // tests candidates, feeds its register window and blends what the window emits front to
 // back (Eq. (1)).  The workgroup leaves the list once no lane is still accumulating.
-// Outputs per pixel: colour, accumulated opacity, exact depth (Sec. 3.2), normal and the
-// replay state the backward pass needs.
+// Outputs per pixel: colour, accumulated opacity, exact depth (Sec. 3.2), normal, the
+// replay state the backward pass needs and two work counters (list entries tested,
+// candidates that passed the alpha cut).
 #include "render_common.h"
 
 namespace sof {
 
 struct PixFwd {
   float T, r, g, b, nx, ny, nz, Tk;
-  int n_emit, k;
+  int n_emit, k, walked, cands;
   bool done;
 };
 
@@ -60,6 +61,7 @@ __global__ __launch_bounds__(TS * TS) void k_render_fwd(RenderFwdArgs a) {
 
   PixFwd p;
   p.T = 1.f; p.r = p.g = p.b = 0.f; p.nx = p.ny = p.nz = 0.f; p.Tk = 0.f; p.n_emit = 0; p.k = -1;
+  p.walked = 0; p.cands = 0;
   p.done = !inside;
   Window<W> win;
   win.init();
@@ -77,7 +79,9 @@ __global__ __launch_bounds__(TS * TS) void k_render_fwd(RenderFwdArgs a) {
       for (int j = 0; j < nb; ++j) {
         const StageEntry e = stage[j];
         float key, al;
+        ++p.walked;
         if (!eval_candidate(e, lx, ly, near_plane, key, al)) continue;
+        ++p.cands;
         float ea;
         uint32_t et;
         if (win.push(key, al, __float_as_uint(e.tag), ea, et)) {
@@ -132,11 +136,13 @@ __global__ __launch_bounds__(TS * TS) void k_render_fwd(RenderFwdArgs a) {
     o[2 * hw + pix] = p.nz;
   }
   if (a.aux) {
-    float* o = a.aux + 4 * ci.pix_off;
+    float* o = a.aux + kAuxChannels * ci.pix_off;
     o[pix] = T;
     o[hw + pix] = __int_as_float(p.n_emit);
     o[2 * hw + pix] = __int_as_float(p.k);
     o[3 * hw + pix] = p.Tk;
+    o[4 * hw + pix] = __int_as_float(p.walked);
+    o[5 * hw + pix] = __int_as_float(p.cands);
   }
 }
 

@@ -16,6 +16,7 @@ constexpr float kTMin = 1e-4f;               // blending stops before T would dr
 constexpr float kHalfLog2e = 0.72134752044448170368f;   // 0.5 * log2(e): exp(-q/2) = exp2(-K q)
 constexpr float kLn2 = 0.69314718055994530942f;
 constexpr int kGradFields = 16;              // per-instance gradient partials
+constexpr int kAuxChannels = 6;              // per-pixel replay state and work counters
 constexpr size_t kAlign = 256;
 
 inline __host__ __device__ size_t align_up(size_t x, size_t a = kAlign) { return (x + a - 1) / a * a; }
@@ -40,16 +41,20 @@ inline __host__ __device__ size_t align_up(size_t x, size_t a = kAlign) { return
 // rect (4 x int16): x0 y0 x1 y1 inclusive pixel rectangle; x0 > x1 when not live
 // zmin (float): mu_z - E sqrt(Sigma_zz), the smallest view z on the E-ellipsoid
 // ------------------------------------------------------------------------------------
+// Query layout (sof_opacity_query): no app / bwdr records; instead one view-independent
+// world record per Gaussian (16 floats): rows of S^-1 R^T (9), mean (3), pad (4), used to
+// evaluate a Gaussian at a point in front of its peak without cancellation.
 struct ProjLayout {
-  size_t geom, app, bwdr, rect, zmin, total;
-  static __host__ __device__ ProjLayout make(int64_t vn) {
+  size_t geom, app, bwdr, rect, zmin, world, total;
+  static __host__ __device__ ProjLayout make(int64_t vn, bool query = false, int64_t n = 0) {
     ProjLayout L;
     size_t o = 0;
     L.geom = o; o = align_up(o + (size_t)vn * 64);
-    L.app = o;  o = align_up(o + (size_t)vn * 32);
-    L.bwdr = o; o = align_up(o + (size_t)vn * 32);
+    L.app = o;  o = align_up(o + (query ? 0 : (size_t)vn * 32));
+    L.bwdr = o; o = align_up(o + (query ? 0 : (size_t)vn * 32));
     L.rect = o; o = align_up(o + (size_t)vn * 8);
     L.zmin = o; o = align_up(o + (size_t)vn * 4);
+    L.world = o; o = align_up(o + (query ? (size_t)n * 64 : 0));
     L.total = o;
     return L;
   }

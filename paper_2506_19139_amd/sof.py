@@ -23,6 +23,7 @@ SOF_DEPTH_GRAD_FULL = 1 << 1
 SOF_QUERY_KEYS = 1 << 2
 
 WINDOWS = (0, 1, 2, 4, 8, 16, 32)
+AUX_CHANNELS = 6      # T_end, n_emitted, k, T_k, entries tested, candidates
 TILES = (8, 16, 32)
 
 
@@ -334,7 +335,7 @@ class Rasterizer:
         P = self.cams.n_pixels
         dev = self.device
         return dict(rgb=torch.empty(3 * P, device=dev), acc=torch.empty(P, device=dev), depth=torch.empty(P, device=dev),
-                    normal=torch.empty(3 * P, device=dev), aux=torch.empty(4 * P, device=dev))
+                    normal=torch.empty(3 * P, device=dev), aux=torch.empty(AUX_CHANNELS * P, device=dev))
 
     def forward(self, g: Gaussians, out=None):
         self.prepare(g)
@@ -381,3 +382,76 @@ class SofRasterize(torch.autograd.Function):
         c = lambda t: None if t is None else t.contiguous()
         gr = ctx.rast.backward(ctx.g, ctx.out, c(d_rgb), c(d_acc), c(d_depth), c(d_normal))
         return gr["means"], gr["scales"], gr["quats"], gr["opac"], gr["sh"], None, None
+
+
+# ------------------------------------------------------------------------------ queries
+
+def query_workspace_size(n, cams: Cameras, opts: Options, n_points, pv_capacity):
+    p, b, s = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
+    o = opts.c_struct()
+    _check(lib().sof_query_workspace_size(n, cams.hp(), len(cams), ctypes.byref(o), n_points, pv_capacity,
+                                          ctypes.byref(p), ctypes.byref(b), ctypes.byref(s)),
+           "sof_query_workspace_size")
+    return p.value, b.value, s.value
+
+
+def opacity_query_raw(g: Gaussians, cams: Cameras, opts: Options, points, pv_capacity, out, proj, bins, sched):
+    gs, o = g.c_struct(), opts.c_struct()
+    n_points = int(points.shape[0])
+    _check(lib().sof_opacity_query(ctypes.byref(gs), cams.hp(), cams.dp(), len(cams), ctypes.byref(o), _ptr(points),
+                                   n_points, int(pv_capacity), _ptr(out), _ptr(proj), proj.numel(), _ptr(bins),
+                                   bins.numel(), _ptr(sched), sched.numel(), _stream()), "sof_opacity_query")
+
+
+class OpacityQuery:
+    """Buffers for repeated opacity-field queries over one camera set.  Instance and
+    (point, view) capacities grow on demand (read-back of the status words, then one rerun)."""
+
+    def __init__(self, cams: Cameras, opts: Options = None, device="cuda", auto_capacity=True):
+        self.cams = cams
+        self.opts = opts or Options()
+        self.device = device
+        self.auto_capacity = auto_capacity
+        self.pv_capacity = 0
+        self.proj = self.bins = self.sched = None
+        self.last = (0, 0)
+
+    def _alloc(self, n, n_points):
+        p, b, s = query_workspace_size(n, self.cams, self.opts, n_points, self.pv_capacity)
+        if self.proj is None or self.proj.numel() < p:
+            self.proj = torch.empty(p, dtype=torch.uint8, device=self.device)
+        if self.bins is None or self.bins.numel() < b:
+            self.bins = torch.empty(b, dtype=torch.uint8, device=self.device)
+        if self.sched is None or self.sched.numel() < s:
+            self.sched = torch.empty(s, dtype=torch.uint8, device=self.device)
+
+    def __call__(self, g: Gaussians, points: torch.Tensor, out=None):
+        n_points = int(points.shape[0])
+        if self.opts.capacity <= 0:
+            self.opts.capacity = max(1024, 2 * g.n * len(self.cams))
+        if self.pv_capacity <= 0:
+            self.pv_capacity = min(n_points * len(self.cams), 2 ** 31 - 1)
+        out = torch.empty(n_points, dtype=torch.float32, device=self.device) if out is None else out
+        for _ in range(3):
+            self._alloc(g.n, n_points)
+            opacity_query_raw(g, self.cams, self.opts, points, self.pv_capacity, out, self.proj, self.bins, self.sched)
+            if not self.auto_capacity:
+                break
+            k_inst, f_inst = read_status(self.bins)
+            k_pv, f_pv = read_status(self.sched)
+            self.last = (k_inst, k_pv)
+            grow = False
+            if k_inst > self.opts.capacity:
+                self.opts.capacity = min(int(k_inst * 1.1) + 1024, 2 ** 31 - 1)
+                grow = True
+            if k_pv > self.pv_capacity:
+                self.pv_capacity = min(int(k_pv * 1.05) + 1024, 2 ** 31 - 1)
+                grow = True
+            if not grow:
+                break
+        return out
+
+
+def opacity_query(g: Gaussians, cams: Cameras, points: torch.Tensor, opts: Options = None):
+    """O(x) = min over views of O_N(x) for every point (one call, fresh buffers)."""
+    return OpacityQuery(cams, opts or Options())(g, points.contiguous())
