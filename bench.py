@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--no-query", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-pixels", type=int, default=160)
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="run one device copy of this many MiB first (scale reference for HBM byte counters)")
     return ap.parse_args()
 
 
@@ -120,6 +122,13 @@ def main():
     from paper_2506_19139_amd import scenes, sof
 
     torch.cuda.set_device(0)
+    if args.calib_copy_mib > 0:
+        n_el = args.calib_copy_mib * (1 << 20) // 4
+        src = torch.ones(n_el, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     log("scene: unbounded 1M")
     scene = scenes.unbounded_scene(args.n, seed=0)
     cam = scenes.circle_camera(0.0, 1920, 1080)

@@ -35,6 +35,7 @@ struct RenderFwdArgs {
   const int2* ranges;
   const uint32_t* vals;     // sorted instance -> emission index
   const int32_t* gid;       // emission index -> Gaussian
+  const uint32_t* recs;     // sorted instances' records in list order
   float* rgb;
   float* acc;
   float* depth;

@@ -6,6 +6,8 @@
 // Outputs per pixel: colour, accumulated opacity, exact depth (Sec. 3.2), normal, the
 // replay state the backward pass needs and two work counters (list entries tested,
 // candidates that passed the alpha cut).
+#include <stdlib.h>
+
 #include "render_common.h"
 
 namespace sof {
@@ -37,6 +39,58 @@ __device__ inline void blend(PixFwd& p, float alpha, uint32_t gid, const float4*
   }
   p.T = test_T;
   ++p.n_emit;
+}
+
+// Depth of the crossing Gaussian and the per-pixel output writes.
+__device__ inline void write_pixel(const RenderFwdArgs& a, const PixFwd& p, const sof_camera& cam, const CamInfo& ci,
+                                   int64_t cam_base, int px, int py) {
+  const int width = cam.width, height = cam.height;
+  // exact depth of the 0.5 level set on the crossing Gaussian (Sec. 3.2, App. A.3)
+  const float rx = (px + 0.5f - cam.cx) / cam.fx, ry = (py + 0.5f - cam.cy) / cam.fy;
+  const float dn = sqrtf(fmaf(rx, rx, fmaf(ry, ry, 1.f)));
+  float depth = 0.f;
+  if (p.k >= 0) {
+    const int64_t vg = cam_base + p.k;
+    const float4 r0 = a.geom[4 * vg], r1 = a.geom[4 * vg + 1], r2 = a.geom[4 * vg + 2], r3 = a.geom[4 * vg + 3];
+    const float2 d = pixel_offset(r0, px, py);
+    const Quad q = quad_terms(r1.x, r1.y, r1.z, r1.w, r2.x, r2.y, r2.z, r2.w, d.x, d.y);
+    const float sstar = r3.x * (1.f + q.b) / q.den;
+    if (a.flags & SOF_DEPTH_MEDIAN) {
+      depth = dn * sstar;
+    } else {
+      const float x = fmaxf(q.num / q.den, 0.f);                 // K q*
+      const float g = (p.Tk - 0.5f) / (p.Tk * r3.y);
+      const float L = fmaxf(2.f * (-x * kLn2 - logf(g)), 0.f);  // 2 ln(G*/g)
+      const float A = r3.w * q.den;                              // d^T P d, d = (x_n, y_n, 1)
+      depth = dn * (sstar - sqrtf(L / A));
+    }
+  }
+  const int64_t hw = (int64_t)width * height;
+  const int64_t pix = (int64_t)py * width + px;
+  const float T = p.T;
+  if (a.rgb) {
+    float* o = a.rgb + 3 * ci.pix_off;
+    o[pix] = fmaf(a.bg[0], T, p.r);
+    o[hw + pix] = fmaf(a.bg[1], T, p.g);
+    o[2 * hw + pix] = fmaf(a.bg[2], T, p.b);
+  }
+  if (a.acc) a.acc[ci.pix_off + pix] = 1.f - T;
+  if (a.depth) a.depth[ci.pix_off + pix] = depth;
+  if (a.normal) {
+    float* o = a.normal + 3 * ci.pix_off;
+    o[pix] = p.nx;
+    o[hw + pix] = p.ny;
+    o[2 * hw + pix] = p.nz;
+  }
+  if (a.aux) {
+    float* o = a.aux + kAuxChannels * ci.pix_off;
+    o[pix] = T;
+    o[hw + pix] = __int_as_float(p.n_emit);
+    o[2 * hw + pix] = __int_as_float(p.k);
+    o[3 * hw + pix] = p.Tk;
+    o[4 * hw + pix] = __int_as_float(p.walked);
+    o[5 * hw + pix] = __int_as_float(p.cands);
+  }
 }
 
 template <int TS, int W>
@@ -97,53 +151,111 @@ __global__ __launch_bounds__(TS * TS) void k_render_fwd(RenderFwdArgs a) {
       if (!p.done && i < win.count) blend(p, win.a[i], win.t[i], a.app, cam_base);
   }
   if (!inside) return;
+  write_pixel(a, p, cam, ci, cam_base, px, py);
+}
 
-  // exact depth of the 0.5 level set on the crossing Gaussian (Sec. 3.2, App. A.3)
-  const float rx = (px + 0.5f - cam.cx) / cam.fx, ry = (py + 0.5f - cam.cy) / cam.fy;
-  const float dn = sqrtf(fmaf(rx, rx, fmaf(ry, ry, 1.f)));
-  float depth = 0.f;
-  if (p.k >= 0) {
-    const int64_t vg = cam_base + p.k;
-    const float4 r0 = a.geom[4 * vg], r1 = a.geom[4 * vg + 1], r2 = a.geom[4 * vg + 2], r3 = a.geom[4 * vg + 3];
-    const float2 d = pixel_offset(r0, px, py);
-    const Quad q = quad_terms(r1.x, r1.y, r1.z, r1.w, r2.x, r2.y, r2.z, r2.w, d.x, d.y);
-    const float sstar = r3.x * (1.f + q.b) / q.den;
-    if (a.flags & SOF_DEPTH_MEDIAN) {
-      depth = dn * sstar;
-    } else {
-      const float x = fmaxf(q.num / q.den, 0.f);                 // K q*
-      const float g = (p.Tk - 0.5f) / (p.Tk * r3.y);
-      const float L = fmaxf(2.f * (-x * kLn2 - logf(g)), 0.f);  // 2 ln(G*/g)
-      const float A = r3.w * q.den;                              // d^T P d, d = (x_n, y_n, 1)
-      depth = dn * (sstar - sqrtf(L / A));
-    }
+// Wave-walk variant: every wave owns an 8x8 sub-tile and walks the tile's materialised
+// records itself with wave-uniform (scalar) loads, skipping entries whose rectangle misses
+// its sub-tile; no LDS and no workgroup barriers, each wave leaves when its lanes are done.
+typedef __attribute__((address_space(4))) const uint32_t ConstU32;
+
+struct RecS {
+  int ui, vi;
+  float hx, hy, gx, gy, cxx, cxy2, cyy, mxx, mxy2, myy, mz, o, thr;
+  uint32_t gid, rx, ry;
+};
+
+__device__ inline RecS load_rec(const uint32_t* recs, int i) {
+  ConstU32* q = (ConstU32*)recs + (size_t)i * kRecWords;
+  RecS r;
+  r.ui = (int)q[0]; r.vi = (int)q[1];
+  r.hx = __uint_as_float(q[2]); r.hy = __uint_as_float(q[3]);
+  r.gx = __uint_as_float(q[4]); r.gy = __uint_as_float(q[5]);
+  r.cxx = __uint_as_float(q[6]); r.cxy2 = __uint_as_float(q[7]);
+  r.cyy = __uint_as_float(q[8]); r.mxx = __uint_as_float(q[9]);
+  r.mxy2 = __uint_as_float(q[10]); r.myy = __uint_as_float(q[11]);
+  r.mz = __uint_as_float(q[12]); r.o = __uint_as_float(q[13]);
+  r.thr = __uint_as_float(q[14]); r.gid = q[15];
+  r.rx = q[16]; r.ry = q[17];
+  return r;
+}
+
+__device__ inline bool eval_candidate_rec(const RecS& e, int px, int py, float near_plane, float& key, float& alpha) {
+  const float dx = (float)(px - e.ui) + e.hx, dy = (float)(py - e.vi) + e.hy;
+  const Quad q = quad_terms(e.gx, e.gy, e.cxx, e.cxy2, e.cyy, e.mxx, e.mxy2, e.myy, dx, dy);
+  if (!(q.den > 0.f)) return false;
+  if (q.num > 1.0001f * e.thr * q.den) return false;
+  const float sn = e.mz * (1.f + q.b);
+  if (!(sn > near_plane * q.den)) return false;
+  const float r = __builtin_amdgcn_rcpf(q.den);
+  const float x = fmaxf(q.num * r, 0.f);
+  alpha = fminf(kAlphaMax, e.o * __builtin_amdgcn_exp2f(-x));
+  if (alpha < kAlphaMin) return false;
+  key = sn * r;
+  return true;
+}
+
+template <int TS, int W>
+__global__ __launch_bounds__(TS * TS) void k_render_fwd_w(RenderFwdArgs a) {
+  constexpr int SUB = TS / 8;
+  const int tile = blockIdx.x;
+  const int c = find_cam(a.cam_info, a.n_cams, tile);
+  const CamInfo ci = a.cam_info[c];
+  const sof_camera& cam = a.cams[c];
+  const int lt = tile - ci.tile_off;
+  const int tx = lt % ci.tiles_x, ty = lt / ci.tiles_x;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int sx0 = tx * TS + (wave % SUB) * 8, sy0 = ty * TS + (wave / SUB) * 8;
+  const int px = sx0 + (lane & 7), py = sy0 + (lane >> 3);
+  const bool inside = px < cam.width && py < cam.height;
+  const int2 rg = a.ranges[tile];
+  const int64_t cam_base = (int64_t)c * a.n;
+  const float near_plane = a.near_plane;
+
+  PixFwd p;
+  p.T = 1.f; p.r = p.g = p.b = 0.f; p.nx = p.ny = p.nz = 0.f; p.Tk = 0.f; p.n_emit = 0; p.k = -1;
+  p.walked = 0; p.cands = 0;
+  p.done = !inside;
+  Window<W> win;
+  win.init();
+  for (int i = rg.x; i < rg.y; ++i) {
+    if (((i - rg.x) & 7) == 0 && __all(p.done)) break;
+    const RecS e = load_rec(a.recs, i);
+    const int rx0 = (int)(e.rx & 0xFFFFu), rx1 = (int)(e.rx >> 16);
+    const int ry0 = (int)(e.ry & 0xFFFFu), ry1 = (int)(e.ry >> 16);
+    if (rx1 < sx0 || rx0 > sx0 + 7 || ry1 < sy0 || ry0 > sy0 + 7) continue;
+    if (p.done) continue;
+    ++p.walked;
+    float key, al;
+    if (!eval_candidate_rec(e, px, py, near_plane, key, al)) continue;
+    ++p.cands;
+    float ea;
+    uint32_t et;
+    if (win.push(key, al, e.gid, ea, et)) blend(p, ea, et, a.app, cam_base);
   }
-  const int64_t hw = (int64_t)width * height;
-  const int64_t pix = (int64_t)py * width + px;
-  const float T = p.T;
-  if (a.rgb) {
-    float* o = a.rgb + 3 * ci.pix_off;
-    o[pix] = fmaf(a.bg[0], T, p.r);
-    o[hw + pix] = fmaf(a.bg[1], T, p.g);
-    o[2 * hw + pix] = fmaf(a.bg[2], T, p.b);
+  if constexpr (W > 0) {
+#pragma unroll
+    for (int i = 0; i < W; ++i)
+      if (!p.done && i < win.count) blend(p, win.a[i], win.t[i], a.app, cam_base);
   }
-  if (a.acc) a.acc[ci.pix_off + pix] = 1.f - T;
-  if (a.depth) a.depth[ci.pix_off + pix] = depth;
-  if (a.normal) {
-    float* o = a.normal + 3 * ci.pix_off;
-    o[pix] = p.nx;
-    o[hw + pix] = p.ny;
-    o[2 * hw + pix] = p.nz;
+  if (!inside) return;
+  write_pixel(a, p, cam, ci, cam_base, px, py);
+}
+
+template <int TS>
+static hipError_t launch_fwd_w(const RenderFwdArgs& a, int window, int64_t n_tiles, hipStream_t s) {
+  const dim3 grid((unsigned)n_tiles), block(TS * TS);
+  switch (window) {
+    case 0: hipLaunchKernelGGL((k_render_fwd_w<TS, 0>), grid, block, 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_render_fwd_w<TS, 1>), grid, block, 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_render_fwd_w<TS, 2>), grid, block, 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_render_fwd_w<TS, 4>), grid, block, 0, s, a); break;
+    case 8: hipLaunchKernelGGL((k_render_fwd_w<TS, 8>), grid, block, 0, s, a); break;
+    case 16: hipLaunchKernelGGL((k_render_fwd_w<TS, 16>), grid, block, 0, s, a); break;
+    case 32: hipLaunchKernelGGL((k_render_fwd_w<TS, 32>), grid, block, 0, s, a); break;
+    default: return hipErrorInvalidValue;
   }
-  if (a.aux) {
-    float* o = a.aux + kAuxChannels * ci.pix_off;
-    o[pix] = T;
-    o[hw + pix] = __int_as_float(p.n_emit);
-    o[2 * hw + pix] = __int_as_float(p.k);
-    o[3 * hw + pix] = p.Tk;
-    o[4 * hw + pix] = __int_as_float(p.walked);
-    o[5 * hw + pix] = __int_as_float(p.cands);
-  }
+  return hipGetLastError();
 }
 
 template <int TS>
@@ -169,6 +281,18 @@ bool render_supported(int tile, int window) {
 
 hipError_t launch_render_fwd(const RenderFwdArgs& a, int tile, int window, int64_t n_tiles, hipStream_t s) {
   if (n_tiles <= 0) return hipSuccess;
+  static const bool wave_walk = [] {
+    const char* e = getenv("SOF_WAVEWALK");
+    return e && e[0] == '1';
+  }();
+  if (wave_walk) {
+    switch (tile) {
+      case 8: return launch_fwd_w<8>(a, window, n_tiles, s);
+      case 16: return launch_fwd_w<16>(a, window, n_tiles, s);
+      case 32: return launch_fwd_w<32>(a, window, n_tiles, s);
+      default: return hipErrorInvalidValue;
+    }
+  }
   switch (tile) {
     case 8: return launch_fwd_ts<8>(a, window, n_tiles, s);
     case 16: return launch_fwd_ts<16>(a, window, n_tiles, s);
