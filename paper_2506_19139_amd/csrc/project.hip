@@ -183,7 +183,7 @@ __global__ __launch_bounds__(256) void k_project(ProjectArgs a) {
   const int j = argmin3(s0, s1, s2);
   double nx = Rg[j], ny = Rg[3 + j], nz = Rg[6 + j];
   if (nx * (ccx - mx) + ny * (ccy - my) + nz * (ccz - mz_w) < 0.0) { nx = -nx; ny = -ny; nz = -nz; }
-  a.app[2 * idx + 0] = make_float4(fmaxf(cr, 0.f), fmaxf(cg, 0.f), fmaxf(cb, 0.f), 0.f);
+  a.app[2 * idx + 0] = make_float4(fmaxf(cr, 0.f), fmaxf(cg, 0.f), fmaxf(cb, 0.f), o);
   a.app[2 * idx + 1] = make_float4((float)nx, (float)ny, (float)nz, 0.f);
 }
 

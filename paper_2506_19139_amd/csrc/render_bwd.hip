@@ -34,7 +34,10 @@ __global__ __launch_bounds__(TS * TS) void k_render_bwd(RenderBwdArgs A) {
   constexpr int B = NT < 256 ? NT : 256;         // list entries staged per batch
   constexpr int NS = 2 * B;                      // resident gradient slots (two batches)
   __shared__ StageEntry stage[B];
-  __shared__ float gsl[kGradFields * NS];
+  constexpr int kSlotStride = kGradFields + 1;   // padded: fields of one slot and equal fields
+                                                 // of neighbouring slots fall in distinct banks
+  constexpr int kGroupReduce = 4;                // lanes sharing an instance: reduce first
+  __shared__ float gsl[kSlotStride * NS];
   const RenderFwdArgs& a = A.f;
   const int tile = blockIdx.x;
   const int c = find_cam(a.cam_info, a.n_cams, tile);
@@ -53,7 +56,7 @@ __global__ __launch_bounds__(TS * TS) void k_render_bwd(RenderBwdArgs A) {
   const float near_plane = a.near_plane;
   const float ifx = 1.f / cam.fx, ify = 1.f / cam.fy;
 
-  for (int s = threadIdx.x; s < kGradFields * NS; s += NT) gsl[s] = 0.f;
+  for (int s = threadIdx.x; s < kSlotStride * NS; s += NT) gsl[s] = 0.f;
 
   // ---- per-pixel forward state and upstream gradients
   const int64_t hw = (int64_t)width * height;
@@ -108,24 +111,25 @@ __global__ __launch_bounds__(TS * TS) void k_render_bwd(RenderBwdArgs A) {
   Window<W> win;
   win.init();
 
-  // one emitted Gaussian: its gradient partials, into LDS or (old entries) the buffer
-  auto emit = [&](float al, uint32_t pos, int cur_b) {
-    const int i = rg.x + (int)pos;
-    const uint32_t e = A.f.vals[i];
-    const int32_t gid = A.f.gid[e];
-    const int64_t vg = cam_base + gid;
-    const float4 r0 = a.geom[4 * vg], r1 = a.geom[4 * vg + 1], r2 = a.geom[4 * vg + 2], r3 = a.geom[4 * vg + 3];
-    const float4 p0 = A.bwdr[2 * vg], p1 = A.bwdr[2 * vg + 1];
-    const float4 col = a.app[2 * vg], nrm = a.app[2 * vg + 1];
-    const float2 dd = pixel_offset(r0, px, py);
-    const float dx = dd.x, dy = dd.y;
-    const Quad q = quad_terms(r1.x, r1.y, r1.z, r1.w, r2.x, r2.y, r2.z, r2.w, dx, dy);
-    const float mz = r3.x, o = r3.y, aa = r3.w;
-    const float iden = 1.f / q.den;
-    const float x = fmaxf(q.num * iden, 0.f);
-    const float G = exp2f(-x);
-    const float sstar = mz * (1.f + q.b) * iden;
+  // Emission (in order, cheap): transmittance, prefix sums and dL/dalpha need only the
+  // Gaussian's colour, normal and opacity.  The chain rule to (mu_c, P_c) and the
+  // accumulation (the expensive part) are queued per lane and run in rounds in which every
+  // lane with pending work takes part, so the wave executes them about max-over-lanes(emitted)
+  // times instead of once per list entry in which any lane emits.
+  constexpr int Q = 4;
+  constexpr uint32_t kCrossBit = 0x80000000u;
+  uint32_t qpos[Q];
+  float qdq[Q], qdo[Q], qw[Q];
+  int qn = 0;
+#pragma unroll
+  for (int k = 0; k < Q; ++k) { qpos[k] = 0u; qdq[k] = 0.f; qdo[k] = 0.f; qw[k] = 0.f; }
+  float k_ds = 0.f, k_dA = 0.f;
 
+  auto emit = [&](float al, uint32_t pos) {
+    const uint32_t e = A.f.vals[rg.x + (int)pos];
+    const int64_t vg = cam_base + A.f.gid[e];
+    const float4 col = a.app[2 * vg], nrm = a.app[2 * vg + 1];
+    const float o = col.w;
     const float Tj = p.T;
     const float w = al * Tj;
     const float om = 1.f - al;
@@ -140,19 +144,48 @@ __global__ __launch_bounds__(TS * TS) void k_render_bwd(RenderBwdArgs A) {
     const float testT = Tj * om;
     const bool is_k = !p.crossed && testT <= 0.5f;
     if (!p.crossed && !is_k) dal -= cT * Tk * iom;
-    const bool clamped = o * G > kAlphaMax;
-    float dq = clamped ? 0.f : -0.5f * al * dal;
-    float dop = clamped ? 0.f : dal * G;
-    float ds = 0.f, dA = 0.f;
+    const bool clamped = al >= kAlphaMax;                 // alpha = min(0.99, o G*)
+    float dq = clamped ? 0.f : -0.5f * al * dal;          // dalpha/dq* = -alpha/2
+    float dop = clamped ? 0.f : dal * (al / o);           // dalpha/do = G*
+    uint32_t tag = pos;
     if (is_k) {
-      ds = gd * dn;
+      k_ds = gd * dn;
+      k_dA = dA_k;
       dq += dq_k;
-      dA = dA_k;
       dop += do_k;
       p.crossed = true;
+      tag |= kCrossBit;
     }
     p.T = testT;
-    // chain to the camera-space mean and precision
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      const bool sel = k == qn;
+      qpos[k] = sel ? tag : qpos[k];
+      qdq[k] = sel ? dq : qdq[k];
+      qdo[k] = sel ? dop : qdo[k];
+      qw[k] = sel ? w : qw[k];
+    }
+    ++qn;
+    if (++p.emitted >= p.n_emit) p.done = true;
+  };
+
+  // One deferred Gaussian: gradients with respect to mu_c and P_c and the colour and
+  // normal partials of this pixel.
+  auto heavy = [&](uint32_t tag, float dq, float dop, float w, float* gv, uint32_t& pos, uint32_t& e) {
+    const bool crossing = (tag & kCrossBit) != 0u;
+    pos = tag & ~kCrossBit;
+    e = A.f.vals[rg.x + (int)pos];
+    const int64_t vg = cam_base + A.f.gid[e];
+    const float4 r0 = a.geom[4 * vg], r1 = a.geom[4 * vg + 1], r2 = a.geom[4 * vg + 2], r3 = a.geom[4 * vg + 3];
+    const float4 p0 = A.bwdr[2 * vg], p1 = A.bwdr[2 * vg + 1];
+    const float2 dd = pixel_offset(r0, px, py);
+    const float dx = dd.x, dy = dd.y;
+    const Quad q = quad_terms(r1.x, r1.y, r1.z, r1.w, r2.x, r2.y, r2.z, r2.w, dx, dy);
+    const float mz = r3.x, aa = r3.w;
+    const float iden = 1.f / q.den;
+    const float sstar = mz * (1.f + q.b) * iden;
+    const float ds = crossing ? k_ds : 0.f;
+    const float dA = crossing ? k_dA : 0.f;
     const float dnx = dx * ifx, dny = dy * ify;
     const float dmx = p1.z, dmy = p1.w;
     const float dvx = dmx + dnx, dvy = dmy + dny;               // d = (dvx, dvy, 1)
@@ -167,7 +200,6 @@ __global__ __launch_bounds__(TS * TS) void k_render_bwd(RenderBwdArgs A) {
     const float Pdz = P02 * dvx + P12 * dvy + P22;
     const float Am = aa * q.den;
     const float sA = ds / Am, hA = 0.5f * sA, dq2 = 2.f * dq;
-    float gv[kGradFields];
     gv[0] = dq2 * Prx + sA * Pdx;
     gv[1] = dq2 * Pry + sA * Pdy;
     gv[2] = dq2 * Prz + sA * Pdz;
@@ -180,17 +212,96 @@ __global__ __launch_bounds__(TS * TS) void k_render_bwd(RenderBwdArgs A) {
     gv[9] = dop;
     gv[10] = gr * w; gv[11] = gg * w; gv[12] = gb * w;
     gv[13] = gnx * w; gv[14] = gny * w; gv[15] = gnz * w;
-    const int resident_from = (cur_b - 1) * B;
-    if ((int)pos >= resident_from) {
-      const int slot = (int)pos % NS;
+  };
+
+  // Every lane with queued work runs one deferred Gaussian; the partials are then added
+  // wave-cooperatively.  Lanes of one wave often hold the same instance (neighbouring
+  // pixels share Gaussians), and float atomics to one LDS address serialise, so lanes are
+  // grouped by instance: small groups add directly, a larger group is first summed across
+  // the wave with a reduce-scatter (each of 16 lanes ends with one field's total) and adds
+  // once.  Entries older than the two resident batches add to the global buffer.
+  auto round = [&](int cur_b) {
+    const bool has = qn > 0;
+    float gv[kGradFields];
+    uint32_t pos = 0xFFFFFFFFu, e = 0u;
 #pragma unroll
-      for (int f = 0; f < kGradFields; ++f) atomicAdd(&gsl[f * NS + slot], gv[f]);
-    } else {
+    for (int f = 0; f < kGradFields; ++f) gv[f] = 0.f;
+    if (has) {
+      --qn;
+      uint32_t tg = 0u;
+      float dq = 0.f, dop = 0.f, w = 0.f;
+#pragma unroll
+      for (int k = 0; k < Q; ++k) {
+        const bool sel = k == qn;
+        tg = sel ? qpos[k] : tg;
+        dq = sel ? qdq[k] : dq;
+        dop = sel ? qdo[k] : dop;
+        w = sel ? qw[k] : w;
+      }
+      heavy(tg, dq, dop, w, gv, pos, e);
+    }
+    const int resident_from = (cur_b - 1) * B;
+    const bool resident = has && (int)pos >= resident_from;
+    if (has && !resident) {
       float* dst = A.grads + (size_t)e * kGradFields;
 #pragma unroll
       for (int f = 0; f < kGradFields; ++f) atomicAdd(dst + f, gv[f]);
     }
-    if (++p.emitted >= p.n_emit) p.done = true;
+    // group the resident lanes by instance
+    uint64_t todo = __ballot(resident);
+    uint64_t big = 0ull;
+    int gsize = 0;
+    while (todo) {
+      const int leader = __ffsll((unsigned long long)todo) - 1;
+      const uint32_t lp = __builtin_amdgcn_readlane(pos, leader);
+      const bool mine = resident && pos == lp;
+      const uint64_t m = __ballot(mine);
+      const int c = __popcll(m);
+      if (mine) gsize = c;
+      if (c >= kGroupReduce) big |= m;
+      todo &= ~m;
+    }
+    if (resident && gsize < kGroupReduce) {
+      float* dst = &gsl[((int)pos % NS) * kSlotStride];
+#pragma unroll
+      for (int f = 0; f < kGradFields; ++f) atomicAdd(dst + f, gv[f]);
+    }
+    const int lane = (int)(threadIdx.x & 63);
+    while (big) {
+      const int leader = __ffsll((unsigned long long)big) - 1;
+      const uint32_t lp = __builtin_amdgcn_readlane(pos, leader);
+      const uint64_t m = __ballot(resident && pos == lp) & big;
+      big &= ~m;
+      const bool mine = (m >> lane) & 1ull;
+      // reduce-scatter over lane bits 5..2: 16 fields -> 1 field per lane
+      float v8[8];
+      const bool b5 = (lane >> 5) & 1, b4 = (lane >> 4) & 1, b3 = (lane >> 3) & 1, b2 = (lane >> 2) & 1;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const float lo = mine ? gv[k] : 0.f, hi = mine ? gv[k + 8] : 0.f;
+        const float recv = __shfl_xor(b5 ? lo : hi, 32);
+        v8[k] = (b5 ? hi : lo) + recv;
+      }
+      float v4[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const float recv = __shfl_xor(b4 ? v8[k] : v8[k + 4], 16);
+        v4[k] = (b4 ? v8[k + 4] : v8[k]) + recv;
+      }
+      float v2[2];
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        const float recv = __shfl_xor(b3 ? v4[k] : v4[k + 2], 8);
+        v2[k] = (b3 ? v4[k + 2] : v4[k]) + recv;
+      }
+      float v1 = (b2 ? v2[1] : v2[0]) + __shfl_xor(b2 ? v2[0] : v2[1], 4);
+      v1 += __shfl_xor(v1, 2);
+      v1 += __shfl_xor(v1, 1);
+      if ((lane & 3) == 0) {
+        const int field = (b5 ? 8 : 0) + (b4 ? 4 : 0) + (b3 ? 2 : 0) + (b2 ? 1 : 0);
+        atomicAdd(&gsl[((int)lp % NS) * kSlotStride + field], v1);
+      }
+    }
   };
 
   // write the resident slots of batch b to the per-instance buffer and clear them
@@ -198,21 +309,20 @@ __global__ __launch_bounds__(TS * TS) void k_render_bwd(RenderBwdArgs A) {
     if (b < 0 || threadIdx.x >= B) return;
     const int pos = b * B + (int)threadIdx.x;
     if (pos >= len) return;
-    const int slot = pos % NS;
+    float* src = &gsl[(pos % NS) * kSlotStride];
     const uint32_t e = A.f.vals[rg.x + pos];
     float4* dst = (float4*)(A.grads + (size_t)e * kGradFields);
 #pragma unroll
     for (int f4 = 0; f4 < kGradFields / 4; ++f4) {
-      dst[f4] = make_float4(gsl[(4 * f4) * NS + slot], gsl[(4 * f4 + 1) * NS + slot], gsl[(4 * f4 + 2) * NS + slot],
-                            gsl[(4 * f4 + 3) * NS + slot]);
+      dst[f4] = make_float4(src[4 * f4], src[4 * f4 + 1], src[4 * f4 + 2], src[4 * f4 + 3]);
 #pragma unroll
-      for (int k = 0; k < 4; ++k) gsl[(4 * f4 + k) * NS + slot] = 0.f;
+      for (int k = 0; k < 4; ++k) src[4 * f4 + k] = 0.f;
     }
   };
 
   int cur_b = -1;
   for (int bs = rg.x; bs < rg.y; bs += B) {
-    if (__syncthreads_count(!p.done) == 0) break;
+    if (__syncthreads_count(!p.done) == 0) break;       // queued work is drained after the loop
     ++cur_b;
     flush(cur_b - 2);
     const int i = bs + (int)threadIdx.x;
@@ -223,25 +333,32 @@ __global__ __launch_bounds__(TS * TS) void k_render_bwd(RenderBwdArgs A) {
     __threadfence();
     __syncthreads();
     const int nb = min(B, rg.y - bs);
-    if (!p.done) {
-      for (int j = 0; j < nb; ++j) {
+    for (int j = 0; j < nb; ++j) {
+      if (!p.done) {
         const StageEntry e = stage[j];
         float key, al;
-        if (!eval_candidate(e, lx, ly, near_plane, key, al)) continue;
-        float ea;
-        uint32_t et;
-        if (win.push(key, al, __float_as_uint(e.tag), ea, et)) {
-          emit(ea, et, cur_b);
-          if (p.done) break;
+        if (eval_candidate(e, lx, ly, near_plane, key, al)) {
+          float ea;
+          uint32_t et;
+          if (win.push(key, al, __float_as_uint(e.tag), ea, et)) emit(ea, et);
         }
       }
+      if (__any(qn == Q)) round(cur_b);
+      if (__all(p.done)) break;
     }
   }
   if constexpr (W > 0) {
-#pragma unroll
-    for (int i = 0; i < W; ++i)
-      if (!p.done && i < win.count) emit(win.a[i], win.t[i], cur_b);
+    while (__any(!p.done && win.count > 0)) {
+      if (!p.done && win.count > 0) {
+        float ea;
+        uint32_t et;
+        win.pop_front(ea, et);
+        emit(ea, et);
+      }
+      if (__any(qn == Q)) round(cur_b);
+    }
   }
+  while (__any(qn > 0)) round(cur_b);
   __syncthreads();
   flush(cur_b - 1);
   flush(cur_b);

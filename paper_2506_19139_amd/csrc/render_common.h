@@ -95,6 +95,21 @@ struct Window {
       t[i] = 0u;
     }
   }
+  // Remove the smallest entry (the head) at the end of the list.
+  __device__ inline void pop_front(float& ea, uint32_t& et) {
+    ea = a[0];
+    et = t[0];
+    if constexpr (W > 1) {
+#pragma unroll
+      for (int i = 0; i < W - 1; ++i) {
+        k[i] = k[i + 1];
+        a[i] = a[i + 1];
+        t[i] = t[i + 1];
+      }
+    }
+    k[W > 0 ? W - 1 : 0] = __builtin_huge_valf();
+    --count;
+  }
   // Feed one candidate.  Returns true with (ea, et) set when an entry leaves the window.
   __device__ inline bool push(float key, float al, uint32_t tag, float& ea, uint32_t& et) {
     if constexpr (W == 0) {

@@ -146,9 +146,12 @@ __global__ __launch_bounds__(TS * TS) void k_render_fwd(RenderFwdArgs a) {
     }
   }
   if constexpr (W > 0) {
-#pragma unroll
-    for (int i = 0; i < W; ++i)
-      if (!p.done && i < win.count) blend(p, win.a[i], win.t[i], a.app, cam_base);
+    while (!p.done && win.count > 0) {
+      float ea;
+      uint32_t et;
+      win.pop_front(ea, et);
+      blend(p, ea, et, a.app, cam_base);
+    }
   }
   if (!inside) return;
   write_pixel(a, p, cam, ci, cam_base, px, py);
@@ -234,9 +237,12 @@ __global__ __launch_bounds__(TS * TS) void k_render_fwd_w(RenderFwdArgs a) {
     if (win.push(key, al, e.gid, ea, et)) blend(p, ea, et, a.app, cam_base);
   }
   if constexpr (W > 0) {
-#pragma unroll
-    for (int i = 0; i < W; ++i)
-      if (!p.done && i < win.count) blend(p, win.a[i], win.t[i], a.app, cam_base);
+    while (!p.done && win.count > 0) {
+      float ea;
+      uint32_t et;
+      win.pop_front(ea, et);
+      blend(p, ea, et, a.app, cam_base);
+    }
   }
   if (!inside) return;
   write_pixel(a, p, cam, ci, cam_base, px, py);

@@ -36,7 +36,7 @@ inline __host__ __device__ size_t align_up(size_t x, size_t a = kAlign) { return
 // dm = (mu_x/mu_z, mu_y/mu_z, 1).  Along the pixel ray d = dm + (dx/fx, dy/fy, 0):
 //   den' = 1 + 2 b' + c' = d^T P d / a,   z-depth of the peak s* = mu_z (1 + b') / den',
 //   G* = exp2(-n'/den'),   q* = n' / (den' 0.5 log2 e).
-// app (8 floats): r g b (linear, clamped >= 0), pad, nx ny nz (world normal), pad
+// app (8 floats): r g b (linear, clamped >= 0), opacity, nx ny nz (world normal), pad
 // bwdr (8 floats): P00 P01 P02 P11 P12 P22 dm_x dm_y   (camera-space precision)
 // rect (4 x int16): x0 y0 x1 y1 inclusive pixel rectangle; x0 > x1 when not live
 // zmin (float): mu_z - E sqrt(Sigma_zz), the smallest view z on the E-ellipsoid
