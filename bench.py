@@ -148,6 +148,7 @@ def main():
     rast.prepare(g)
     opts.capacity = int(rast.last_count * 1.25) + 4096
     rast.auto_capacity = False
+    rast._alloc(g.n)
     out = rast.alloc_outputs()
     grads = dict(means=torch.empty_like(g.means), scales=torch.empty_like(g.scales), quats=torch.empty_like(g.quats),
                  opac=torch.empty_like(g.opac), sh=torch.empty_like(g.sh))

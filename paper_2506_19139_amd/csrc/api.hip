@@ -143,10 +143,10 @@ static int fill_fwd_args(int64_t n, const sof_camera* h_cams, const sof_camera* 
   a->flags = opts->flags;
   a->geom = (const float4*)(pb + P.geom);
   a->app = (const float4*)(pb + P.app);
+  a->rect = (const short4*)(pb + P.rect);
   a->ranges = (const int2*)(bb + B.ranges);
   a->vals = (const uint32_t*)(bb + (sorted_parity(n_tiles) ? B.vals1 : B.vals0));
   a->gid = (const int32_t*)(bb + B.gid);
-  a->recs = (const uint32_t*)(bb + B.recs);
   *n_tiles_out = n_tiles;
   return SOF_OK;
 }

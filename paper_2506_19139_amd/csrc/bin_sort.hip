@@ -289,35 +289,6 @@ __global__ __launch_bounds__(256) void k_ranges(const uint64_t* keys, const int6
   if (i == n - 1 || (uint32_t)(keys[i + 1] >> 32) != t) ranges[t].y = (int)(i + 1);
 }
 
-// Materialise each sorted instance's geometry in list order so the rasteriser can walk a
-// tile's list with contiguous, wave-uniform loads.
-__global__ __launch_bounds__(256) void k_gather_recs(const uint64_t* keys, const uint32_t* vals, const int32_t* gid,
-                                                     const float4* geom, const short4* rect, const CamInfo* ci,
-                                                     int n_cams, int64_t n, const int64_t* count, int64_t cap,
-                                                     uint32_t* recs) {
-  const int64_t kk = live_count(count, cap);
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= kk) return;
-  const int tile = (int)(keys[i] >> 32);
-  int lo = 0, hi = n_cams - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (ci[mid].tile_off <= tile) lo = mid; else hi = mid - 1;
-  }
-  const int32_t g = gid[vals[i]];
-  const int64_t vg = (int64_t)lo * n + g;
-  const float4 r0 = geom[4 * vg], r1 = geom[4 * vg + 1], r2 = geom[4 * vg + 2], r3 = geom[4 * vg + 3];
-  const short4 rc = rect[vg];
-  uint4* dst = (uint4*)(recs + (size_t)i * kRecWords);
-  dst[0] = make_uint4(__float_as_uint(r0.x), __float_as_uint(r0.z), __float_as_uint(0.5f - r0.y),
-                      __float_as_uint(0.5f - r0.w));
-  dst[1] = make_uint4(__float_as_uint(r1.x), __float_as_uint(r1.y), __float_as_uint(r1.z), __float_as_uint(r1.w));
-  dst[2] = make_uint4(__float_as_uint(r2.x), __float_as_uint(r2.y), __float_as_uint(r2.z), __float_as_uint(r2.w));
-  dst[3] = make_uint4(__float_as_uint(r3.x), __float_as_uint(r3.y), __float_as_uint(r3.z), (uint32_t)g);
-  dst[4] = make_uint4((uint32_t)(uint16_t)rc.x | ((uint32_t)(uint16_t)rc.z << 16),
-                      (uint32_t)(uint16_t)rc.y | ((uint32_t)(uint16_t)rc.w << 16), 0u, 0u);
-}
-
 hipError_t launch_cam_table(const sof_camera* d_cams, int n_cams, int tile, CamInfo* out, StatusBlock* status,
                             hipStream_t s) {
   hipLaunchKernelGGL(k_cam_table, dim3(1), dim3(64), 0, s, d_cams, n_cams, tile, out, status);
@@ -366,9 +337,6 @@ hipError_t launch_bin_sort(int64_t n, const sof_camera* d_cams, int n_cams, int6
   hipLaunchKernelGGL(k_fill_ranges, dim3((unsigned)div_up(n_tiles > 0 ? n_tiles : 1, th)), dim3(th), 0, s, ranges, n_tiles);
   if (cap > 0) {
     hipLaunchKernelGGL(k_ranges, dim3((unsigned)div_up(cap, th)), dim3(th), 0, s, ks, &status->count, cap, ranges);
-    if (!query_keys)
-      hipLaunchKernelGGL(k_gather_recs, dim3((unsigned)div_up(cap, th)), dim3(th), 0, s, ks, *parity ? v1 : v0, gid,
-                         geom, rect, cams, n_cams, n, &status->count, cap, (uint32_t*)(bb + B.recs));
   }
   return hipGetLastError();
 }

@@ -32,10 +32,10 @@ struct RenderFwdArgs {
   uint32_t flags;
   const float4* geom;
   const float4* app;
+  const short4* rect;
   const int2* ranges;
   const uint32_t* vals;     // sorted instance -> emission index
   const int32_t* gid;       // emission index -> Gaussian
-  const uint32_t* recs;     // sorted instances' records in list order
   float* rgb;
   float* acc;
   float* depth;

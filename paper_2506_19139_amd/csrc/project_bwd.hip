@@ -9,11 +9,27 @@
 
 namespace sof {
 
-__global__ __launch_bounds__(128) void k_project_bwd(ProjectBwdArgs a) {
+constexpr int kPbThreads = 128;
+
+// Copy a [rows, width] float block staged in LDS to consecutive rows of a global array
+// with coalesced stores (one row per thread would stride the writes).
+__device__ inline void store_rows(const float* lds, float* dst, int64_t row0, int rows, int width) {
+  const int total = rows * width;
+  float* out = dst + row0 * width;
+  for (int k = threadIdx.x; k < total; k += kPbThreads) out[k] = lds[k];
+}
+
+template <int DEG>
+__global__ __launch_bounds__(kPbThreads) void k_project_bwd(ProjectBwdArgs a) {
+  __shared__ float s_sh[kPbThreads * kMaxShCoeffs * 3];
+  __shared__ float s_small[kPbThreads * 11];        // dmu 3, ds 3, dq 4, do 1
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= a.n) return;
-  const int deg = a.sh_degree;
-  const int K = (deg + 1) * (deg + 1);
+  const int64_t row0 = (int64_t)blockIdx.x * blockDim.x;
+  const int rows = (int)((a.n - row0) < kPbThreads ? (a.n - row0) : kPbThreads);
+  constexpr int K = (DEG + 1) * (DEG + 1);
+  constexpr int K3 = 3 * K;
+  constexpr int deg = DEG;
+  if (i < a.n) {
   const int64_t kinst = *a.count_total < a.cap ? *a.count_total : a.cap;
 
   const double mx = a.means[3 * i], my = a.means[3 * i + 1], mzw = a.means[3 * i + 2];
@@ -30,8 +46,9 @@ __global__ __launch_bounds__(128) void k_project_bwd(ProjectBwdArgs a) {
   double dPw[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   double dRg[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   double dop = 0.0;
-  float dsh[kMaxShCoeffs * 3];
-  for (int k = 0; k < K * 3; ++k) dsh[k] = 0.f;
+  float dsh[K3];
+#pragma unroll
+  for (int k = 0; k < K3; ++k) dsh[k] = 0.f;
 
   for (int c = 0; c < a.n_cams; ++c) {
     const int64_t vg = (int64_t)c * a.n + i;
@@ -75,6 +92,7 @@ __global__ __launch_bounds__(128) void k_project_bwd(ProjectBwdArgs a) {
     float Y[kMaxShCoeffs];
     sh_basis(deg, dx, dy, dz, Y);
     float cr = 0.5f, cg = 0.5f, cb = 0.5f;
+#pragma unroll
     for (int k = 0; k < K; ++k) {
       cr = fmaf(Y[k], f[3 * k], cr);
       cg = fmaf(Y[k], f[3 * k + 1], cg);
@@ -82,6 +100,7 @@ __global__ __launch_bounds__(128) void k_project_bwd(ProjectBwdArgs a) {
     }
     const float gc[3] = {cr > 0.f ? gsum[10] : 0.f, cg > 0.f ? gsum[11] : 0.f, cb > 0.f ? gsum[12] : 0.f};
     float wk[kMaxShCoeffs];
+#pragma unroll
     for (int k = 0; k < K; ++k) {
       dsh[3 * k] += Y[k] * gc[0];
       dsh[3 * k + 1] += Y[k] * gc[1];
@@ -126,19 +145,39 @@ __global__ __launch_bounds__(128) void k_project_bwd(ProjectBwdArgs a) {
   dq[3] = 2.0 * (-2.0 * z * g[0] - w * g[1] + x * g[2] + w * g[3] - 2.0 * z * g[4] + y * g[5] + x * g[6] + y * g[7]);
   const double qd = w * dq[0] + x * dq[1] + y * dq[2] + z * dq[3];
   const double qv[4] = {w, x, y, z};
-  for (int k = 0; k < 4; ++k) a.d_quats[4 * i + k] = (float)((dq[k] - qv[k] * qd) / qnorm);
+  float* sm = s_small + threadIdx.x * 11;
   for (int k = 0; k < 3; ++k) {
-    a.d_means[3 * i + k] = (float)dmu[k];
-    a.d_scales[3 * i + k] = (float)ds[k];
+    sm[k] = (float)dmu[k];
+    sm[3 + k] = (float)ds[k];
   }
-  a.d_opac[i] = (float)dop;
-  for (int k = 0; k < K * 3; ++k) a.d_sh[(size_t)i * K * 3 + k] = dsh[k];
+  for (int k = 0; k < 4; ++k) sm[6 + k] = (float)((dq[k] - qv[k] * qd) / qnorm);
+  sm[10] = (float)dop;
+#pragma unroll
+  for (int k = 0; k < K3; ++k) s_sh[threadIdx.x * K3 + k] = dsh[k];
+  }
+  __syncthreads();
+  if (rows <= 0) return;
+  // coalesced write-out of the block's rows
+  for (int k = threadIdx.x; k < rows * 3; k += kPbThreads) {
+    const int r = k / 3, c = k - 3 * r;
+    a.d_means[row0 * 3 + k] = s_small[r * 11 + c];
+    a.d_scales[row0 * 3 + k] = s_small[r * 11 + 3 + c];
+  }
+  for (int k = threadIdx.x; k < rows * 4; k += kPbThreads) a.d_quats[row0 * 4 + k] = s_small[(k >> 2) * 11 + 6 + (k & 3)];
+  for (int k = threadIdx.x; k < rows; k += kPbThreads) a.d_opac[row0 + k] = s_small[k * 11 + 10];
+  store_rows(s_sh, a.d_sh, row0, rows, K3);
 }
 
 hipError_t launch_project_bwd(const ProjectBwdArgs& a, hipStream_t s) {
   if (a.n <= 0) return hipSuccess;
-  const int th = 128;
-  hipLaunchKernelGGL(k_project_bwd, dim3((unsigned)div_up(a.n, th)), dim3(th), 0, s, a);
+  const int th = kPbThreads;
+  const dim3 grid((unsigned)div_up(a.n, th)), block(th);
+  switch (a.sh_degree) {
+    case 0: hipLaunchKernelGGL(k_project_bwd<0>, grid, block, 0, s, a); break;
+    case 1: hipLaunchKernelGGL(k_project_bwd<1>, grid, block, 0, s, a); break;
+    case 2: hipLaunchKernelGGL(k_project_bwd<2>, grid, block, 0, s, a); break;
+    default: hipLaunchKernelGGL(k_project_bwd<3>, grid, block, 0, s, a); break;
+  }
   return hipGetLastError();
 }
 

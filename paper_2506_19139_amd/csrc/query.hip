@@ -153,6 +153,8 @@ struct __align__(16) StageQ {
   float mz, o, thr, zmin;
   float m[9];
   float mu[3];
+  uint32_t rx, ry;      // pixel rectangle x0 | x1 << 16, y0 | y1 << 16
+  uint32_t pad0, pad1;
 };
 
 struct QueryArgs {
@@ -165,6 +167,7 @@ struct QueryArgs {
   const float4* geom;
   const float* zmin;
   const float4* world;
+  const short4* rect;
   const int2* granges;          // Gaussian tile lists
   const uint32_t* gvals;
   const int32_t* ggid;
@@ -229,6 +232,10 @@ __global__ __launch_bounds__(kQueryBlock) void k_query_eval(QueryArgs a) {
         e.m[0] = w0.x; e.m[1] = w0.y; e.m[2] = w0.z; e.m[3] = w0.w;
         e.m[4] = w1.x; e.m[5] = w1.y; e.m[6] = w1.z; e.m[7] = w1.w;
         e.m[8] = w2.x; e.mu[0] = w2.y; e.mu[1] = w2.z; e.mu[2] = w2.w;
+        const short4 rc = a.rect[vg];
+        e.rx = (uint32_t)(uint16_t)rc.x | ((uint32_t)(uint16_t)rc.z << 16);
+        e.ry = (uint32_t)(uint16_t)rc.y | ((uint32_t)(uint16_t)rc.w << 16);
+        e.pad0 = 0u; e.pad1 = 0u;
         stage[threadIdx.x] = e;
       }
       __syncthreads();
@@ -237,6 +244,10 @@ __global__ __launch_bounds__(kQueryBlock) void k_query_eval(QueryArgs a) {
         for (int j = 0; j < nb; ++j) {
           const StageQ& e = stage[j];
           if (e.zmin > zx) { done = true; break; }
+          // the point's pixel must lie in the Gaussian's (conservative) rectangle
+          if (uxi < (int)(e.rx & 0xFFFFu) || uxi > (int)(e.rx >> 16) || vyi < (int)(e.ry & 0xFFFFu) ||
+              vyi > (int)(e.ry >> 16))
+            continue;
           const float dx = (float)(uxi - e.ui) + (uxf - e.uf);
           const float dy = (float)(vyi - e.vi) + (vyf - e.vf);
           const Quad q = quad_terms(e.gx, e.gy, e.cxx, e.cxy2, e.cyy, e.mxx, e.mxy2, e.myy, dx, dy);
@@ -379,6 +390,7 @@ int sof_opacity_query(const sof_gaussians* g, const sof_camera* h_cams, const so
   qa.pts = points; qa.cams = d_cams; qa.cam_info = ci; qa.n_cams = n_cams; qa.near_plane = near_plane; qa.n = n;
   qa.geom = (const float4*)(pbase + P.geom);
   qa.zmin = (const float*)(pbase + P.zmin);
+  qa.rect = (const short4*)(pbase + P.rect);
   qa.world = (const float4*)(pbase + P.world);
   qa.granges = (const int2*)(bbase + B.ranges);
   qa.gvals = (const uint32_t*)(bbase + (gpar ? B.vals1 : B.vals0));

@@ -31,13 +31,15 @@ struct PixBwd {
 template <int TS, int W>
 __global__ __launch_bounds__(TS * TS) void k_render_bwd(RenderBwdArgs A) {
   constexpr int NT = TS * TS;
-  constexpr int B = NT < 256 ? NT : 256;         // list entries staged per batch
+  constexpr int B = NT < 128 ? NT : 128;         // list entries staged per batch
   constexpr int NS = 2 * B;                      // resident gradient slots (two batches)
   __shared__ StageEntry stage[B];
   constexpr int kSlotStride = kGradFields + 1;   // padded: fields of one slot and equal fields
                                                  // of neighbouring slots fall in distinct banks
   constexpr int kGroupReduce = 4;                // lanes sharing an instance: reduce first
   __shared__ float gsl[kSlotStride * NS];
+  __shared__ uint32_t ring_e[NS];                // emission index of each resident list slot
+  __shared__ int32_t ring_g[NS];                 // and its Gaussian
   const RenderFwdArgs& a = A.f;
   const int tile = blockIdx.x;
   const int c = find_cam(a.cam_info, a.n_cams, tile);
@@ -46,9 +48,11 @@ __global__ __launch_bounds__(TS * TS) void k_render_bwd(RenderBwdArgs A) {
   const int width = cam.width, height = cam.height;
   const int lt = tile - ci.tile_off;
   const int tx = lt % ci.tiles_x, ty = lt / ci.tiles_x;
-  const int lx = threadIdx.x % TS, ly = threadIdx.x / TS;
+  int lx, ly;
+  lane_pixel<TS>((int)threadIdx.x, lx, ly);
   const int x0 = tx * TS, y0 = ty * TS;
   const int px = x0 + lx, py = y0 + ly;
+  const int sx = x0 + (lx & ~7), sy = y0 + (ly & ~7);     // this wave's 8x8 sub-tile
   const bool inside = px < width && py < height;
   const int2 rg = A.f.ranges[tile];
   const int len = rg.y - rg.x;
@@ -125,9 +129,19 @@ __global__ __launch_bounds__(TS * TS) void k_render_bwd(RenderBwdArgs A) {
   for (int k = 0; k < Q; ++k) { qpos[k] = 0u; qdq[k] = 0.f; qdo[k] = 0.f; qw[k] = 0.f; }
   float k_ds = 0.f, k_dA = 0.f;
 
-  auto emit = [&](float al, uint32_t pos) {
-    const uint32_t e = A.f.vals[rg.x + (int)pos];
-    const int64_t vg = cam_base + A.f.gid[e];
+  // Gaussian of list slot `pos`: from the LDS ring while its batch is resident
+  auto slot_gaussian = [&](uint32_t pos, int cur_b, uint32_t& e) -> int32_t {
+    if ((int)pos >= (cur_b - 1) * B) {
+      e = ring_e[pos % NS];
+      return ring_g[pos % NS];
+    }
+    e = A.f.vals[rg.x + (int)pos];
+    return A.f.gid[e];
+  };
+
+  auto emit = [&](float al, uint32_t pos, int cur_b) {
+    uint32_t e;
+    const int64_t vg = cam_base + slot_gaussian(pos, cur_b, e);
     const float4 col = a.app[2 * vg], nrm = a.app[2 * vg + 1];
     const float o = col.w;
     const float Tj = p.T;
@@ -171,11 +185,10 @@ __global__ __launch_bounds__(TS * TS) void k_render_bwd(RenderBwdArgs A) {
 
   // One deferred Gaussian: gradients with respect to mu_c and P_c and the colour and
   // normal partials of this pixel.
-  auto heavy = [&](uint32_t tag, float dq, float dop, float w, float* gv, uint32_t& pos, uint32_t& e) {
+  auto heavy = [&](uint32_t tag, float dq, float dop, float w, float* gv, uint32_t& pos, uint32_t& e, int cur_b) {
     const bool crossing = (tag & kCrossBit) != 0u;
     pos = tag & ~kCrossBit;
-    e = A.f.vals[rg.x + (int)pos];
-    const int64_t vg = cam_base + A.f.gid[e];
+    const int64_t vg = cam_base + slot_gaussian(pos, cur_b, e);
     const float4 r0 = a.geom[4 * vg], r1 = a.geom[4 * vg + 1], r2 = a.geom[4 * vg + 2], r3 = a.geom[4 * vg + 3];
     const float4 p0 = A.bwdr[2 * vg], p1 = A.bwdr[2 * vg + 1];
     const float2 dd = pixel_offset(r0, px, py);
@@ -238,7 +251,7 @@ __global__ __launch_bounds__(TS * TS) void k_render_bwd(RenderBwdArgs A) {
         dop = sel ? qdo[k] : dop;
         w = sel ? qw[k] : w;
       }
-      heavy(tg, dq, dop, w, gv, pos, e);
+      heavy(tg, dq, dop, w, gv, pos, e, cur_b);
     }
     const int resident_from = (cur_b - 1) * B;
     const bool resident = has && (int)pos >= resident_from;
@@ -327,20 +340,23 @@ __global__ __launch_bounds__(TS * TS) void k_render_bwd(RenderBwdArgs A) {
     flush(cur_b - 2);
     const int i = bs + (int)threadIdx.x;
     if (threadIdx.x < B && i < rg.y) {
-      const int32_t g = A.f.gid[A.f.vals[i]];
-      stage_entry(a.geom, cam_base + g, x0, y0, (uint32_t)(i - rg.x), &stage[threadIdx.x]);
+      const uint32_t e = A.f.vals[i];
+      const int32_t g = A.f.gid[e];
+      stage_entry(a.geom, a.rect, cam_base + g, x0, y0, (uint32_t)(i - rg.x), &stage[threadIdx.x]);
+      ring_e[(i - rg.x) % NS] = e;
+      ring_g[(i - rg.x) % NS] = g;
     }
     __threadfence();
     __syncthreads();
     const int nb = min(B, rg.y - bs);
     for (int j = 0; j < nb; ++j) {
-      if (!p.done) {
-        const StageEntry e = stage[j];
+      const StageEntry e = stage[j];
+      if (!p.done && !misses_subtile(e, sx, sy)) {
         float key, al;
         if (eval_candidate(e, lx, ly, near_plane, key, al)) {
           float ea;
           uint32_t et;
-          if (win.push(key, al, __float_as_uint(e.tag), ea, et)) emit(ea, et);
+          if (win.push(key, al, __float_as_uint(e.tag), ea, et)) emit(ea, et, cur_b);
         }
       }
       if (__any(qn == Q)) round(cur_b);
@@ -353,7 +369,7 @@ __global__ __launch_bounds__(TS * TS) void k_render_bwd(RenderBwdArgs A) {
         float ea;
         uint32_t et;
         win.pop_front(ea, et);
-        emit(ea, et);
+        emit(ea, et, cur_b);
       }
       if (__any(qn == Q)) round(cur_b);
     }

@@ -6,8 +6,6 @@
 // Outputs per pixel: colour, accumulated opacity, exact depth (Sec. 3.2), normal, the
 // replay state the backward pass needs and two work counters (list entries tested,
 // candidates that passed the alpha cut).
-#include <stdlib.h>
-
 #include "render_common.h"
 
 namespace sof {
@@ -105,9 +103,11 @@ __global__ __launch_bounds__(TS * TS) void k_render_fwd(RenderFwdArgs a) {
   const int width = cam.width, height = cam.height;
   const int lt = tile - ci.tile_off;
   const int tx = lt % ci.tiles_x, ty = lt / ci.tiles_x;
-  const int lx = threadIdx.x % TS, ly = threadIdx.x / TS;
+  int lx, ly;
+  lane_pixel<TS>((int)threadIdx.x, lx, ly);
   const int x0 = tx * TS, y0 = ty * TS;
   const int px = x0 + lx, py = y0 + ly;
+  const int sx = x0 + (lx & ~7), sy = y0 + (ly & ~7);     // this wave's 8x8 sub-tile
   const bool inside = px < width && py < height;
   const int2 rg = a.ranges[tile];
   const int64_t cam_base = (int64_t)c * a.n;
@@ -125,13 +125,14 @@ __global__ __launch_bounds__(TS * TS) void k_render_fwd(RenderFwdArgs a) {
     const int i = bs + (int)threadIdx.x;
     if (threadIdx.x < B && i < rg.y) {
       const int32_t g = a.gid[a.vals[i]];
-      stage_entry(a.geom, cam_base + g, x0, y0, (uint32_t)g, &stage[threadIdx.x]);
+      stage_entry(a.geom, a.rect, cam_base + g, x0, y0, (uint32_t)g, &stage[threadIdx.x]);
     }
     __syncthreads();
     const int nb = min(B, rg.y - bs);
     if (!p.done) {
       for (int j = 0; j < nb; ++j) {
         const StageEntry e = stage[j];
+        if (misses_subtile(e, sx, sy)) continue;
         float key, al;
         ++p.walked;
         if (!eval_candidate(e, lx, ly, near_plane, key, al)) continue;
@@ -157,113 +158,6 @@ __global__ __launch_bounds__(TS * TS) void k_render_fwd(RenderFwdArgs a) {
   write_pixel(a, p, cam, ci, cam_base, px, py);
 }
 
-// Wave-walk variant: every wave owns an 8x8 sub-tile and walks the tile's materialised
-// records itself with wave-uniform (scalar) loads, skipping entries whose rectangle misses
-// its sub-tile; no LDS and no workgroup barriers, each wave leaves when its lanes are done.
-typedef __attribute__((address_space(4))) const uint32_t ConstU32;
-
-struct RecS {
-  int ui, vi;
-  float hx, hy, gx, gy, cxx, cxy2, cyy, mxx, mxy2, myy, mz, o, thr;
-  uint32_t gid, rx, ry;
-};
-
-__device__ inline RecS load_rec(const uint32_t* recs, int i) {
-  ConstU32* q = (ConstU32*)recs + (size_t)i * kRecWords;
-  RecS r;
-  r.ui = (int)q[0]; r.vi = (int)q[1];
-  r.hx = __uint_as_float(q[2]); r.hy = __uint_as_float(q[3]);
-  r.gx = __uint_as_float(q[4]); r.gy = __uint_as_float(q[5]);
-  r.cxx = __uint_as_float(q[6]); r.cxy2 = __uint_as_float(q[7]);
-  r.cyy = __uint_as_float(q[8]); r.mxx = __uint_as_float(q[9]);
-  r.mxy2 = __uint_as_float(q[10]); r.myy = __uint_as_float(q[11]);
-  r.mz = __uint_as_float(q[12]); r.o = __uint_as_float(q[13]);
-  r.thr = __uint_as_float(q[14]); r.gid = q[15];
-  r.rx = q[16]; r.ry = q[17];
-  return r;
-}
-
-__device__ inline bool eval_candidate_rec(const RecS& e, int px, int py, float near_plane, float& key, float& alpha) {
-  const float dx = (float)(px - e.ui) + e.hx, dy = (float)(py - e.vi) + e.hy;
-  const Quad q = quad_terms(e.gx, e.gy, e.cxx, e.cxy2, e.cyy, e.mxx, e.mxy2, e.myy, dx, dy);
-  if (!(q.den > 0.f)) return false;
-  if (q.num > 1.0001f * e.thr * q.den) return false;
-  const float sn = e.mz * (1.f + q.b);
-  if (!(sn > near_plane * q.den)) return false;
-  const float r = __builtin_amdgcn_rcpf(q.den);
-  const float x = fmaxf(q.num * r, 0.f);
-  alpha = fminf(kAlphaMax, e.o * __builtin_amdgcn_exp2f(-x));
-  if (alpha < kAlphaMin) return false;
-  key = sn * r;
-  return true;
-}
-
-template <int TS, int W>
-__global__ __launch_bounds__(TS * TS) void k_render_fwd_w(RenderFwdArgs a) {
-  constexpr int SUB = TS / 8;
-  const int tile = blockIdx.x;
-  const int c = find_cam(a.cam_info, a.n_cams, tile);
-  const CamInfo ci = a.cam_info[c];
-  const sof_camera& cam = a.cams[c];
-  const int lt = tile - ci.tile_off;
-  const int tx = lt % ci.tiles_x, ty = lt / ci.tiles_x;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int sx0 = tx * TS + (wave % SUB) * 8, sy0 = ty * TS + (wave / SUB) * 8;
-  const int px = sx0 + (lane & 7), py = sy0 + (lane >> 3);
-  const bool inside = px < cam.width && py < cam.height;
-  const int2 rg = a.ranges[tile];
-  const int64_t cam_base = (int64_t)c * a.n;
-  const float near_plane = a.near_plane;
-
-  PixFwd p;
-  p.T = 1.f; p.r = p.g = p.b = 0.f; p.nx = p.ny = p.nz = 0.f; p.Tk = 0.f; p.n_emit = 0; p.k = -1;
-  p.walked = 0; p.cands = 0;
-  p.done = !inside;
-  Window<W> win;
-  win.init();
-  for (int i = rg.x; i < rg.y; ++i) {
-    if (((i - rg.x) & 7) == 0 && __all(p.done)) break;
-    const RecS e = load_rec(a.recs, i);
-    const int rx0 = (int)(e.rx & 0xFFFFu), rx1 = (int)(e.rx >> 16);
-    const int ry0 = (int)(e.ry & 0xFFFFu), ry1 = (int)(e.ry >> 16);
-    if (rx1 < sx0 || rx0 > sx0 + 7 || ry1 < sy0 || ry0 > sy0 + 7) continue;
-    if (p.done) continue;
-    ++p.walked;
-    float key, al;
-    if (!eval_candidate_rec(e, px, py, near_plane, key, al)) continue;
-    ++p.cands;
-    float ea;
-    uint32_t et;
-    if (win.push(key, al, e.gid, ea, et)) blend(p, ea, et, a.app, cam_base);
-  }
-  if constexpr (W > 0) {
-    while (!p.done && win.count > 0) {
-      float ea;
-      uint32_t et;
-      win.pop_front(ea, et);
-      blend(p, ea, et, a.app, cam_base);
-    }
-  }
-  if (!inside) return;
-  write_pixel(a, p, cam, ci, cam_base, px, py);
-}
-
-template <int TS>
-static hipError_t launch_fwd_w(const RenderFwdArgs& a, int window, int64_t n_tiles, hipStream_t s) {
-  const dim3 grid((unsigned)n_tiles), block(TS * TS);
-  switch (window) {
-    case 0: hipLaunchKernelGGL((k_render_fwd_w<TS, 0>), grid, block, 0, s, a); break;
-    case 1: hipLaunchKernelGGL((k_render_fwd_w<TS, 1>), grid, block, 0, s, a); break;
-    case 2: hipLaunchKernelGGL((k_render_fwd_w<TS, 2>), grid, block, 0, s, a); break;
-    case 4: hipLaunchKernelGGL((k_render_fwd_w<TS, 4>), grid, block, 0, s, a); break;
-    case 8: hipLaunchKernelGGL((k_render_fwd_w<TS, 8>), grid, block, 0, s, a); break;
-    case 16: hipLaunchKernelGGL((k_render_fwd_w<TS, 16>), grid, block, 0, s, a); break;
-    case 32: hipLaunchKernelGGL((k_render_fwd_w<TS, 32>), grid, block, 0, s, a); break;
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
-}
-
 template <int TS>
 static hipError_t launch_fwd_ts(const RenderFwdArgs& a, int window, int64_t n_tiles, hipStream_t s) {
   const dim3 grid((unsigned)n_tiles), block(TS * TS);
@@ -287,18 +181,6 @@ bool render_supported(int tile, int window) {
 
 hipError_t launch_render_fwd(const RenderFwdArgs& a, int tile, int window, int64_t n_tiles, hipStream_t s) {
   if (n_tiles <= 0) return hipSuccess;
-  static const bool wave_walk = [] {
-    const char* e = getenv("SOF_WAVEWALK");
-    return e && e[0] == '1';
-  }();
-  if (wave_walk) {
-    switch (tile) {
-      case 8: return launch_fwd_w<8>(a, window, n_tiles, s);
-      case 16: return launch_fwd_w<16>(a, window, n_tiles, s);
-      case 32: return launch_fwd_w<32>(a, window, n_tiles, s);
-      default: return hipErrorInvalidValue;
-    }
-  }
   switch (tile) {
     case 8: return launch_fwd_ts<8>(a, window, n_tiles, s);
     case 16: return launch_fwd_ts<16>(a, window, n_tiles, s);

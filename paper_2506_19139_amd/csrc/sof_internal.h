@@ -77,12 +77,6 @@ struct StatusBlock {
   int64_t aux[30];
 };
 
-// Sorted tile-instance records, materialised in list order for the per-pixel walk
-// (20 dwords): u_int, v_int, 0.5 - u_frac, 0.5 - v_frac, gx, gy, cxx, 2cxy, cyy, mxx, 2mxy,
-// myy, mu_z, o, log2(255 o), Gaussian index, x0 | x1 << 16, y0 | y1 << 16, pad, pad.
-constexpr int kRecWords = 20;
-constexpr int kRecBytes = kRecWords * 4;
-
 constexpr int kSortItems = 8;                    // keys per thread in a radix sort tile
 constexpr int kSortThreads = 256;
 constexpr int kSortTile = kSortItems * kSortThreads;
@@ -95,7 +89,7 @@ inline __host__ __device__ int64_t div_up(int64_t a, int64_t b) { return (a + b 
 // bins buffer layout.
 struct BinsLayout {
   size_t status, cams, counts, offsets, scan_tmp, keys0, keys1, vals0, vals1, gid, hist, hist_tmp,
-      ranges, recs, total;
+      ranges, total;
   int64_t vn, cap, n_tiles, sort_blocks;
   static __host__ __device__ BinsLayout make(int64_t vn, int32_t n_cams, int64_t cap, int64_t n_tiles) {
     BinsLayout L;
@@ -116,7 +110,6 @@ struct BinsLayout {
     L.hist = o;     o = align_up(o + (size_t)hn * 4);
     L.hist_tmp = o; o = align_up(o + (size_t)(div_up(hn, kScanChunk) + 1) * 8);
     L.ranges = o;   o = align_up(o + (size_t)(n_tiles > 0 ? n_tiles : 1) * 8);
-    L.recs = o;     o = align_up(o + (size_t)cap * kRecBytes);
     L.total = o;
     return L;
   }
