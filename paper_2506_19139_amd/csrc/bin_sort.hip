@@ -137,12 +137,18 @@ template <typename K>
 __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const K* keys_in, const uint32_t* vals_in, K* keys_out,
                                                                 uint32_t* vals_out, const int64_t* count, int64_t cap,
                                                                 int shift, const int32_t* hist, int64_t nblocks) {
-  __shared__ int32_t wc[4][256];
+  __shared__ int32_t wc[4][256];       // per-wave digit counts, then per-wave block-local offsets
+  __shared__ int32_t lstart[256];      // block-local start of each digit
+  __shared__ int32_t gbase[256];       // global start of this block's run of each digit
+  __shared__ int32_t lw[4];
+  __shared__ K skey[kSortTile];
+  __shared__ uint32_t sval[kSortTile];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   for (int t = threadIdx.x; t < 4 * 256; t += kSortThreads) (&wc[0][0])[t] = 0;
   __syncthreads();
   const int64_t n = live_count(count, cap);
-  const int64_t start = (int64_t)blockIdx.x * kSortTile + (int64_t)w * (kSortItems * 64);
+  const int64_t bstart = (int64_t)blockIdx.x * kSortTile;
+  const int64_t start = bstart + (int64_t)w * (kSortItems * 64);
   K key[kSortItems];
   uint32_t val[kSortItems];
   int rank[kSortItems];
@@ -170,25 +176,39 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const K* keys_in
   }
   __syncthreads();
   {
+    // block-local digit starts (scan over digits) and per-wave offsets inside each digit
     const int t = threadIdx.x;
-    int run = hist[(int64_t)t * nblocks + blockIdx.x];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int c = wc[k][t];
-      wc[k][t] = run;
-      run += c;
-    }
+    const int c0 = wc[0][t], c1 = wc[1][t], c2 = wc[2][t], c3 = wc[3][t];
+    int total;
+    const int ls = block_exclusive_scan<int, int>(c0 + c1 + c2 + c3, lw, total);
+    lstart[t] = ls;
+    gbase[t] = hist[(int64_t)t * nblocks + blockIdx.x];
+    wc[0][t] = ls;
+    wc[1][t] = ls + c0;
+    wc[2][t] = ls + c0 + c1;
+    wc[3][t] = ls + c0 + c1 + c2;
   }
   __syncthreads();
+  // block-local stable sort in LDS
 #pragma unroll
   for (int it = 0; it < kSortItems; ++it) {
     const int64_t idx = start + it * 64 + lane;
     if (idx < n) {
       const int d = (int)((key[it] >> shift) & 0xFF);
-      const int64_t dst = (int64_t)wc[w][d] + rank[it];
-      keys_out[dst] = key[it];
-      vals_out[dst] = val[it];
+      const int lp = wc[w][d] + rank[it];
+      skey[lp] = key[it];
+      sval[lp] = val[it];
     }
+  }
+  __syncthreads();
+  // write out: consecutive local positions of one digit go to consecutive global slots
+  const int nloc = (int)((n - bstart) < kSortTile ? (n - bstart > 0 ? n - bstart : 0) : kSortTile);
+  for (int sidx = threadIdx.x; sidx < nloc; sidx += kSortThreads) {
+    const K k = skey[sidx];
+    const int d = (int)((k >> shift) & 0xFF);
+    const int64_t dst = (int64_t)gbase[d] + (sidx - lstart[d]);
+    keys_out[dst] = k;
+    vals_out[dst] = sval[sidx];
   }
 }
 

@@ -240,36 +240,41 @@ __global__ __launch_bounds__(kQueryBlock) void k_query_eval(QueryArgs a) {
       }
       __syncthreads();
       const int nb = min(kQueryBlock, gr.y - gs);
-      if (!done) {
-        for (int j = 0; j < nb; ++j) {
-          const StageQ& e = stage[j];
-          if (e.zmin > zx) { done = true; break; }
-          // the point's pixel must lie in the Gaussian's (conservative) rectangle
-          if (uxi < (int)(e.rx & 0xFFFFu) || uxi > (int)(e.rx >> 16) || vyi < (int)(e.ry & 0xFFFFu) ||
-              vyi > (int)(e.ry >> 16))
-            continue;
-          const float dx = (float)(uxi - e.ui) + (uxf - e.uf);
-          const float dy = (float)(vyi - e.vi) + (vyf - e.vf);
-          const Quad q = quad_terms(e.gx, e.gy, e.cxx, e.cxy2, e.cyy, e.mxx, e.mxy2, e.myy, dx, dy);
-          if (!(q.den > 0.f)) continue;
-          if (q.num > 1.0001f * e.thr * q.den) continue;       // q* already beyond the cutoff
-          const float sn = e.mz * (1.f + q.b);
-          float xk;
-          if (sn < zx * q.den) {                                 // peak in front of the point
-            if (!(sn > a.near_plane * q.den)) continue;
-            xk = fmaxf(q.num / q.den, 0.f);
-          } else {                                               // evaluate at the point itself
-            const float wx = px - e.mu[0], wy = py - e.mu[1], wz = pz - e.mu[2];
-            const float g0 = fmaf(e.m[0], wx, fmaf(e.m[1], wy, e.m[2] * wz));
-            const float g1 = fmaf(e.m[3], wx, fmaf(e.m[4], wy, e.m[5] * wz));
-            const float g2 = fmaf(e.m[6], wx, fmaf(e.m[7], wy, e.m[8] * wz));
-            xk = kHalfLog2e * fmaf(g0, g0, fmaf(g1, g1, g2 * g2));
-          }
-          const float al = fminf(kAlphaMax, e.o * exp2f(-xk));
-          if (al < kAlphaMin) continue;
-          T *= 1.f - al;
-          if (1.f - T >= cur) { done = true; pruned = true; break; }
+      // Branch-light walk: lanes keep per-entry decisions as predicates and only wave-uniform
+      // branches skip work (divergent branches cost scalar exec-mask instructions per entry,
+      // which bound this loop otherwise).
+      for (int j = 0; j < nb; ++j) {
+        if (!__any(!done)) break;
+        const StageQ& e = stage[j];
+        const float zmin = e.zmin;
+        const uint32_t rx = e.rx, ry = e.ry;
+        done = done || (zmin > zx);                    // lists are sorted by z_min
+        const bool in = !done && uxi >= (int)(rx & 0xFFFFu) && uxi <= (int)(rx >> 16) &&
+                        vyi >= (int)(ry & 0xFFFFu) && vyi <= (int)(ry >> 16);
+        if (!__any(in)) continue;
+        const float dx = (float)(uxi - e.ui) + (uxf - e.uf);
+        const float dy = (float)(vyi - e.vi) + (vyf - e.vf);
+        const Quad q = quad_terms(e.gx, e.gy, e.cxx, e.cxy2, e.cyy, e.mxx, e.mxy2, e.myy, dx, dy);
+        const float sn = e.mz * (1.f + q.b);
+        bool ok = in && (q.den > 0.f) && !(q.num > 1.0001f * e.thr * q.den);
+        const bool before = sn < zx * q.den;                       // peak in front of the point
+        ok = ok && (!before || sn > a.near_plane * q.den);
+        float xk = fmaxf(q.num / q.den, 0.f);
+        const bool atx = ok && !before;                            // evaluate at the point itself
+        if (__any(atx)) {
+          const float wx = px - e.mu[0], wy = py - e.mu[1], wz = pz - e.mu[2];
+          const float g0 = fmaf(e.m[0], wx, fmaf(e.m[1], wy, e.m[2] * wz));
+          const float g1 = fmaf(e.m[3], wx, fmaf(e.m[4], wy, e.m[5] * wz));
+          const float g2 = fmaf(e.m[6], wx, fmaf(e.m[7], wy, e.m[8] * wz));
+          const float xa = kHalfLog2e * fmaf(g0, g0, fmaf(g1, g1, g2 * g2));
+          xk = atx ? xa : xk;
         }
+        const float al = fminf(kAlphaMax, e.o * exp2f(-xk));
+        ok = ok && al >= kAlphaMin;
+        T = ok ? T * (1.f - al) : T;
+        const bool prune = ok && (1.f - T >= cur);
+        pruned = pruned || prune;
+        done = done || prune;
       }
     }
     if (active && !pruned) atomicMin((unsigned int*)(a.out + p), __float_as_uint(1.f - T));

@@ -34,6 +34,7 @@ __global__ __launch_bounds__(TS * TS) void k_render_bwd(RenderBwdArgs A) {
   constexpr int B = NT < 128 ? NT : 128;         // list entries staged per batch
   constexpr int NS = 2 * B;                      // resident gradient slots (two batches)
   __shared__ StageEntry stage[B];
+  __shared__ uint2 srect[B];
   constexpr int kSlotStride = kGradFields + 1;   // padded: fields of one slot and equal fields
                                                  // of neighbouring slots fall in distinct banks
   constexpr int kGroupReduce = 4;                // lanes sharing an instance: reduce first
@@ -342,7 +343,8 @@ __global__ __launch_bounds__(TS * TS) void k_render_bwd(RenderBwdArgs A) {
     if (threadIdx.x < B && i < rg.y) {
       const uint32_t e = A.f.vals[i];
       const int32_t g = A.f.gid[e];
-      stage_entry(a.geom, a.rect, cam_base + g, x0, y0, (uint32_t)(i - rg.x), &stage[threadIdx.x]);
+      stage_entry(a.geom, a.rect, cam_base + g, x0, y0, (uint32_t)(i - rg.x), &stage[threadIdx.x],
+                  &srect[threadIdx.x]);
       ring_e[(i - rg.x) % NS] = e;
       ring_g[(i - rg.x) % NS] = g;
     }
@@ -350,8 +352,8 @@ __global__ __launch_bounds__(TS * TS) void k_render_bwd(RenderBwdArgs A) {
     __syncthreads();
     const int nb = min(B, rg.y - bs);
     for (int j = 0; j < nb; ++j) {
-      const StageEntry e = stage[j];
-      if (!p.done && !misses_subtile(e, sx, sy)) {
+      if (!p.done && !misses_subtile(srect[j], sx, sy)) {
+        const StageEntry e = stage[j];
         float key, al;
         if (eval_candidate(e, lx, ly, near_plane, key, al)) {
           float ea;

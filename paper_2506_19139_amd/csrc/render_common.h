@@ -14,23 +14,22 @@
 
 namespace sof {
 
-// LDS copy of a tile-list entry (20 words): integer and fractional parts of the pixel
-// offset of the tile origin from the projected centre, the quadric constants, a 32-bit tag
-// (Gaussian index or list slot) and the Gaussian's pixel rectangle.  A pixel's offset is
-// (float)(ix + lx) + hx: exact integer arithmetic and a single rounding, independent of the
-// tile size.
+// LDS copy of a tile-list entry (16 words): integer and fractional parts of the pixel
+// offset of the tile origin from the projected centre, the quadric constants and a 32-bit
+// tag (Gaussian index or list slot).  A pixel's offset is (float)(ix + lx) + hx: exact
+// integer arithmetic and a single rounding, independent of the tile size.  The entry's
+// pixel rectangle is staged separately (8 bytes) so that a wave whose sub-tile it misses
+// reads nothing else.
 struct __align__(16) StageEntry {
   int ix, iy;
   float hx, hy, gx, gy;
   float cxx, cxy2, cyy, mxx;
   float mxy2, myy, mz, o;
   float thr, tag;
-  uint32_t rx, ry;      // x0 | x1 << 16, y0 | y1 << 16 (inclusive, pixels)
-  uint32_t pad0, pad1;
 };
 
 __device__ inline void stage_entry(const float4* geom, const short4* rect, int64_t vg, int x0, int y0, uint32_t tag,
-                                   StageEntry* dst) {
+                                   StageEntry* dst, uint2* dst_rect) {
   const float4 r0 = geom[4 * vg + 0], r1 = geom[4 * vg + 1], r2 = geom[4 * vg + 2], r3 = geom[4 * vg + 3];
   const short4 rc = rect[vg];
   StageEntry e;
@@ -41,10 +40,9 @@ __device__ inline void stage_entry(const float4* geom, const short4* rect, int64
   e.gx = r1.x; e.gy = r1.y; e.cxx = r1.z; e.cxy2 = r1.w;
   e.cyy = r2.x; e.mxx = r2.y; e.mxy2 = r2.z; e.myy = r2.w;
   e.mz = r3.x; e.o = r3.y; e.thr = r3.z; e.tag = __uint_as_float(tag);
-  e.rx = (uint32_t)(uint16_t)rc.x | ((uint32_t)(uint16_t)rc.z << 16);
-  e.ry = (uint32_t)(uint16_t)rc.y | ((uint32_t)(uint16_t)rc.w << 16);
-  e.pad0 = 0u; e.pad1 = 0u;
   *dst = e;
+  *dst_rect = make_uint2((uint32_t)(uint16_t)rc.x | ((uint32_t)(uint16_t)rc.z << 16),
+                         (uint32_t)(uint16_t)rc.y | ((uint32_t)(uint16_t)rc.w << 16));
 }
 
 // Pixel-to-lane layout inside a TS x TS tile: wave w owns the 8x8 sub-tile
@@ -58,9 +56,9 @@ __device__ inline void lane_pixel(int tid, int& lx, int& ly) {
 
 // True when the entry's rectangle misses the 8x8 sub-tile with origin (sx, sy) (then no
 // pixel of the sub-tile can have it as a candidate).
-__device__ inline bool misses_subtile(const StageEntry& e, int sx, int sy) {
-  const int rx0 = (int)(e.rx & 0xFFFFu), rx1 = (int)(e.rx >> 16);
-  const int ry0 = (int)(e.ry & 0xFFFFu), ry1 = (int)(e.ry >> 16);
+__device__ inline bool misses_subtile(uint2 r, int sx, int sy) {
+  const int rx0 = (int)(r.x & 0xFFFFu), rx1 = (int)(r.x >> 16);
+  const int ry0 = (int)(r.y & 0xFFFFu), ry1 = (int)(r.y >> 16);
   return rx1 < sx || rx0 > sx + 7 || ry1 < sy || ry0 > sy + 7;
 }
 

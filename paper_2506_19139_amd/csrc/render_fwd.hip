@@ -96,6 +96,7 @@ __global__ __launch_bounds__(TS * TS) void k_render_fwd(RenderFwdArgs a) {
   constexpr int NT = TS * TS;
   constexpr int B = NT < 256 ? NT : 256;         // list entries staged per batch
   __shared__ StageEntry stage[B];
+  __shared__ uint2 srect[B];
   const int tile = blockIdx.x;
   const int c = find_cam(a.cam_info, a.n_cams, tile);
   const CamInfo ci = a.cam_info[c];
@@ -125,14 +126,14 @@ __global__ __launch_bounds__(TS * TS) void k_render_fwd(RenderFwdArgs a) {
     const int i = bs + (int)threadIdx.x;
     if (threadIdx.x < B && i < rg.y) {
       const int32_t g = a.gid[a.vals[i]];
-      stage_entry(a.geom, a.rect, cam_base + g, x0, y0, (uint32_t)g, &stage[threadIdx.x]);
+      stage_entry(a.geom, a.rect, cam_base + g, x0, y0, (uint32_t)g, &stage[threadIdx.x], &srect[threadIdx.x]);
     }
     __syncthreads();
     const int nb = min(B, rg.y - bs);
     if (!p.done) {
       for (int j = 0; j < nb; ++j) {
+        if (misses_subtile(srect[j], sx, sy)) continue;
         const StageEntry e = stage[j];
-        if (misses_subtile(e, sx, sy)) continue;
         float key, al;
         ++p.walked;
         if (!eval_candidate(e, lx, ly, near_plane, key, al)) continue;
