@@ -54,6 +54,7 @@ __global__ __launch_bounds__(TS * TS) void k_render_bwd(RenderBwdArgs A) {
   const int x0 = tx * TS, y0 = ty * TS;
   const int px = x0 + lx, py = y0 + ly;
   const int sx = x0 + (lx & ~7), sy = y0 + (ly & ~7);     // this wave's 8x8 sub-tile
+  const int sxu = __builtin_amdgcn_readfirstlane(sx), syu = __builtin_amdgcn_readfirstlane(sy);
   const bool inside = px < width && py < height;
   const int2 rg = A.f.ranges[tile];
   const int len = rg.y - rg.x;
@@ -352,17 +353,21 @@ __global__ __launch_bounds__(TS * TS) void k_render_bwd(RenderBwdArgs A) {
     __syncthreads();
     const int nb = min(B, rg.y - bs);
     for (int j = 0; j < nb; ++j) {
-      if (!p.done && !misses_subtile(srect[j], sx, sy)) {
-        const StageEntry e = stage[j];
-        float key, al;
-        if (eval_candidate(e, lx, ly, near_plane, key, al)) {
+      if (!__any(!p.done)) break;
+      if (misses_subtile(uniform_rect(srect[j]), sxu, syu)) continue;      // wave-uniform
+      const StageEntry e = stage[j];
+      const Cand1 c1 = candidate_stage1(e, lx, ly, near_plane);
+      if (!__any(c1.pre && !p.done)) continue;
+      float key, al;
+      const bool cand = candidate_stage2(e, c1, key, al) && !p.done;
+      if (__any(cand)) {
+        if (cand) {
           float ea;
           uint32_t et;
           if (win.push(key, al, __float_as_uint(e.tag), ea, et)) emit(ea, et, cur_b);
         }
+        if (__any(qn == Q)) round(cur_b);
       }
-      if (__any(qn == Q)) round(cur_b);
-      if (__all(p.done)) break;
     }
   }
   if constexpr (W > 0) {

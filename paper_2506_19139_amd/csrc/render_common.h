@@ -84,23 +84,38 @@ __device__ inline Quad quad_terms(float gx, float gy, float cxx, float cxy2, flo
   return q;
 }
 
-// Candidate test: alpha = min(0.99, o G*) >= 1/255 and the peak's view z beyond the near
-// plane.  key = view z of the peak (the pixel's ray distance t* divided by |d|, so the
-// per-pixel order is the order of t*).
-__device__ inline bool eval_candidate(const StageEntry& e, int lx, int ly, float near_plane, float& key,
-                                      float& alpha) {
+// Candidate test in two predicated stages (no early returns: divergent branches cost scalar
+// exec-mask instructions per list entry).  Stage 1 (cheap): the quadric terms, the
+// conservative alpha pre-cut and the near-plane test of the peak.  Stage 2: alpha =
+// min(0.99, o G*) >= 1/255 and the key (view z of the peak; the pixel's ray distance t* is
+// key |d|, so the per-pixel order is the order of t*).  Callers skip stage 2 with a
+// wave-uniform branch when no lane passed stage 1.
+struct Cand1 {
+  Quad q;
+  float sn;
+  bool pre;
+};
+
+__device__ inline Cand1 candidate_stage1(const StageEntry& e, int lx, int ly, float near_plane) {
+  Cand1 c;
   const float dx = (float)(e.ix + lx) + e.hx, dy = (float)(e.iy + ly) + e.hy;
-  const Quad q = quad_terms(e.gx, e.gy, e.cxx, e.cxy2, e.cyy, e.mxx, e.mxy2, e.myy, dx, dy);
-  if (!(q.den > 0.f)) return false;
-  if (q.num > 1.0001f * e.thr * q.den) return false;          // conservative pre-cut
-  const float sn = e.mz * (1.f + q.b);
-  if (!(sn > near_plane * q.den)) return false;
-  const float r = __builtin_amdgcn_rcpf(q.den);
-  const float x = fmaxf(q.num * r, 0.f);
+  c.q = quad_terms(e.gx, e.gy, e.cxx, e.cxy2, e.cyy, e.mxx, e.mxy2, e.myy, dx, dy);
+  c.sn = e.mz * (1.f + c.q.b);
+  c.pre = (c.q.den > 0.f) && !(c.q.num > 1.0001f * e.thr * c.q.den) && (c.sn > near_plane * c.q.den);
+  return c;
+}
+
+__device__ inline bool candidate_stage2(const StageEntry& e, const Cand1& c, float& key, float& alpha) {
+  const float r = __builtin_amdgcn_rcpf(c.q.den);
+  const float x = fmaxf(c.q.num * r, 0.f);
   alpha = fminf(kAlphaMax, e.o * __builtin_amdgcn_exp2f(-x));
-  if (alpha < kAlphaMin) return false;
-  key = sn * r;
-  return true;
+  key = c.sn * r;
+  return c.pre && alpha >= kAlphaMin;
+}
+
+// Wave-uniform copy of a staged rectangle (every lane reads the same LDS word).
+__device__ inline uint2 uniform_rect(uint2 r) {
+  return make_uint2(__builtin_amdgcn_readfirstlane(r.x), __builtin_amdgcn_readfirstlane(r.y));
 }
 
 template <int W>

@@ -109,6 +109,7 @@ __global__ __launch_bounds__(TS * TS) void k_render_fwd(RenderFwdArgs a) {
   const int x0 = tx * TS, y0 = ty * TS;
   const int px = x0 + lx, py = y0 + ly;
   const int sx = x0 + (lx & ~7), sy = y0 + (ly & ~7);     // this wave's 8x8 sub-tile
+  const int sxu = __builtin_amdgcn_readfirstlane(sx), syu = __builtin_amdgcn_readfirstlane(sy);
   const bool inside = px < width && py < height;
   const int2 rg = a.ranges[tile];
   const int64_t cam_base = (int64_t)c * a.n;
@@ -130,20 +131,21 @@ __global__ __launch_bounds__(TS * TS) void k_render_fwd(RenderFwdArgs a) {
     }
     __syncthreads();
     const int nb = min(B, rg.y - bs);
-    if (!p.done) {
-      for (int j = 0; j < nb; ++j) {
-        if (misses_subtile(srect[j], sx, sy)) continue;
-        const StageEntry e = stage[j];
-        float key, al;
-        ++p.walked;
-        if (!eval_candidate(e, lx, ly, near_plane, key, al)) continue;
+    for (int j = 0; j < nb; ++j) {
+      if (!__any(!p.done)) break;
+      if (misses_subtile(uniform_rect(srect[j]), sxu, syu)) continue;      // wave-uniform
+      const StageEntry e = stage[j];
+      p.walked += p.done ? 0 : 1;
+      const Cand1 c1 = candidate_stage1(e, lx, ly, near_plane);
+      if (!__any(c1.pre && !p.done)) continue;
+      float key, al;
+      const bool cand = candidate_stage2(e, c1, key, al) && !p.done;
+      if (!__any(cand)) continue;
+      if (cand) {
         ++p.cands;
         float ea;
         uint32_t et;
-        if (win.push(key, al, __float_as_uint(e.tag), ea, et)) {
-          blend(p, ea, et, a.app, cam_base);
-          if (p.done) break;
-        }
+        if (win.push(key, al, __float_as_uint(e.tag), ea, et)) blend(p, ea, et, a.app, cam_base);
       }
     }
   }
