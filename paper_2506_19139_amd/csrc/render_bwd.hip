@@ -117,18 +117,17 @@ __global__ __launch_bounds__(TS * TS) void k_render_bwd(RenderBwdArgs A) {
   Window<W> win;
   win.init();
 
-  // Emission (in order, cheap): transmittance, prefix sums and dL/dalpha need only the
-  // Gaussian's colour, normal and opacity.  The chain rule to (mu_c, P_c) and the
-  // accumulation (the expensive part) are queued per lane and run in rounds in which every
-  // lane with pending work takes part, so the wave executes them about max-over-lanes(emitted)
-  // times instead of once per list entry in which any lane emits.
-  constexpr int Q = 4;
+  // Emission, in the forward's order: transmittance, prefix sums and dL/dalpha need only the
+  // Gaussian's colour, normal and opacity; they leave (tag, dq, dop, w) in the lane's
+  // pending slot.  The chain rule to (mu_c, P_c) and the accumulation then run once per list
+  // step for all lanes that emitted in it, so lanes holding the same Gaussian can be summed
+  // across the wave before touching LDS.
   constexpr uint32_t kCrossBit = 0x80000000u;
-  uint32_t qpos[Q];
-  float qdq[Q], qdo[Q], qw[Q];
-  int qn = 0;
-#pragma unroll
-  for (int k = 0; k < Q; ++k) { qpos[k] = 0u; qdq[k] = 0.f; qdo[k] = 0.f; qw[k] = 0.f; }
+  bool has = false;
+  uint32_t qtag = 0u;
+  float qdq = 0.f, qdo = 0.f, qw = 0.f;
+  uint32_t qe = 0u;
+  int32_t qg = 0;
   float k_ds = 0.f, k_dA = 0.f;
 
   // Gaussian of list slot `pos`: from the LDS ring while its batch is resident
@@ -143,7 +142,8 @@ __global__ __launch_bounds__(TS * TS) void k_render_bwd(RenderBwdArgs A) {
 
   auto emit = [&](float al, uint32_t pos, int cur_b) {
     uint32_t e;
-    const int64_t vg = cam_base + slot_gaussian(pos, cur_b, e);
+    const int32_t g = slot_gaussian(pos, cur_b, e);
+    const int64_t vg = cam_base + g;
     const float4 col = a.app[2 * vg], nrm = a.app[2 * vg + 1];
     const float o = col.w;
     const float Tj = p.T;
@@ -173,24 +173,21 @@ __global__ __launch_bounds__(TS * TS) void k_render_bwd(RenderBwdArgs A) {
       tag |= kCrossBit;
     }
     p.T = testT;
-#pragma unroll
-    for (int k = 0; k < Q; ++k) {
-      const bool sel = k == qn;
-      qpos[k] = sel ? tag : qpos[k];
-      qdq[k] = sel ? dq : qdq[k];
-      qdo[k] = sel ? dop : qdo[k];
-      qw[k] = sel ? w : qw[k];
-    }
-    ++qn;
+    has = true;
+    qtag = tag;
+    qdq = dq;
+    qdo = dop;
+    qw = w;
+    qe = e;
+    qg = g;
     if (++p.emitted >= p.n_emit) p.done = true;
   };
 
-  // One deferred Gaussian: gradients with respect to mu_c and P_c and the colour and
+  // One emitted Gaussian: gradients with respect to mu_c and P_c and the colour and
   // normal partials of this pixel.
-  auto heavy = [&](uint32_t tag, float dq, float dop, float w, float* gv, uint32_t& pos, uint32_t& e, int cur_b) {
+  auto heavy = [&](uint32_t tag, float dq, float dop, float w, float* gv) {
     const bool crossing = (tag & kCrossBit) != 0u;
-    pos = tag & ~kCrossBit;
-    const int64_t vg = cam_base + slot_gaussian(pos, cur_b, e);
+    const int64_t vg = cam_base + qg;
     const float4 r0 = a.geom[4 * vg], r1 = a.geom[4 * vg + 1], r2 = a.geom[4 * vg + 2], r3 = a.geom[4 * vg + 3];
     const float4 p0 = A.bwdr[2 * vg], p1 = A.bwdr[2 * vg + 1];
     const float2 dd = pixel_offset(r0, px, py);
@@ -229,32 +226,19 @@ __global__ __launch_bounds__(TS * TS) void k_render_bwd(RenderBwdArgs A) {
     gv[13] = gnx * w; gv[14] = gny * w; gv[15] = gnz * w;
   };
 
-  // Every lane with queued work runs one deferred Gaussian; the partials are then added
+  // Every lane with a pending Gaussian computes its partials; they are then added
   // wave-cooperatively.  Lanes of one wave often hold the same instance (neighbouring
   // pixels share Gaussians), and float atomics to one LDS address serialise, so lanes are
   // grouped by instance: small groups add directly, a larger group is first summed across
   // the wave with a reduce-scatter (each of 16 lanes ends with one field's total) and adds
   // once.  Entries older than the two resident batches add to the global buffer.
   auto round = [&](int cur_b) {
-    const bool has = qn > 0;
     float gv[kGradFields];
-    uint32_t pos = 0xFFFFFFFFu, e = 0u;
+    const uint32_t pos = has ? (qtag & ~kCrossBit) : 0xFFFFFFFFu;
+    const uint32_t e = qe;
 #pragma unroll
     for (int f = 0; f < kGradFields; ++f) gv[f] = 0.f;
-    if (has) {
-      --qn;
-      uint32_t tg = 0u;
-      float dq = 0.f, dop = 0.f, w = 0.f;
-#pragma unroll
-      for (int k = 0; k < Q; ++k) {
-        const bool sel = k == qn;
-        tg = sel ? qpos[k] : tg;
-        dq = sel ? qdq[k] : dq;
-        dop = sel ? qdo[k] : dop;
-        w = sel ? qw[k] : w;
-      }
-      heavy(tg, dq, dop, w, gv, pos, e, cur_b);
-    }
+    if (has) heavy(qtag, qdq, qdo, qw, gv);
     const int resident_from = (cur_b - 1) * B;
     const bool resident = has && (int)pos >= resident_from;
     if (has && !resident) {
@@ -317,6 +301,7 @@ __global__ __launch_bounds__(TS * TS) void k_render_bwd(RenderBwdArgs A) {
         atomicAdd(&gsl[((int)lp % NS) * kSlotStride + field], v1);
       }
     }
+    has = false;
   };
 
   // write the resident slots of batch b to the per-instance buffer and clear them
@@ -337,7 +322,7 @@ __global__ __launch_bounds__(TS * TS) void k_render_bwd(RenderBwdArgs A) {
 
   int cur_b = -1;
   for (int bs = rg.x; bs < rg.y; bs += B) {
-    if (__syncthreads_count(!p.done) == 0) break;       // queued work is drained after the loop
+    if (__syncthreads_count(!p.done) == 0) break;       // window contents are drained after the loop
     ++cur_b;
     flush(cur_b - 2);
     const int i = bs + (int)threadIdx.x;
@@ -366,7 +351,7 @@ __global__ __launch_bounds__(TS * TS) void k_render_bwd(RenderBwdArgs A) {
           uint32_t et;
           if (win.push(key, al, __float_as_uint(e.tag), ea, et)) emit(ea, et, cur_b);
         }
-        if (__any(qn == Q)) round(cur_b);
+        if (__any(has)) round(cur_b);
       }
     }
   }
@@ -378,10 +363,9 @@ __global__ __launch_bounds__(TS * TS) void k_render_bwd(RenderBwdArgs A) {
         win.pop_front(ea, et);
         emit(ea, et, cur_b);
       }
-      if (__any(qn == Q)) round(cur_b);
+      if (__any(has)) round(cur_b);
     }
   }
-  while (__any(qn > 0)) round(cur_b);
   __syncthreads();
   flush(cur_b - 1);
   flush(cur_b);
