@@ -36,6 +36,38 @@ FLOP_BLEND = 15     # one blended Gaussian: transmittance, weight, colour and no
 FLOP_ADJ = 110      # one replayed Gaussian in the backward: dalpha, chain to (mu_c, P_c), partials
 
 
+# HBM traffic of the rasteriser kernels, from two rocprofv3 --pmc passes (FETCH_SIZE, then
+# WRITE_SIZE) over this benchmark with its default arguments, in KiB per dispatch, each scaled by
+# what the same counter reads for a 1 GiB device copy (--calib-copy-mib 1024).  A figure is
+# reported only while the kernel's sources hash to the value the counters were taken with.
+KERNEL_SOURCES = {
+    "k_render_fwd": ("render_fwd.hip", "render_common.h", "sof_internal.h", "launch.h"),
+    "k_render_bwd": ("render_bwd.hip", "render_common.h", "sof_internal.h", "launch.h"),
+}
+COUNTERS = {                        # kernel -> sources hash, counter KiB per dispatch
+    "k_render_bwd": {"src": "cdbfbee793385fca", "fetch_kib": 586162.7, "write_kib": 258460.2},
+    "k_render_fwd": {"src": "703224e307dc2bbe", "fetch_kib": 332043.8, "write_kib": 124426.9},
+}
+COUNTER_SCALE = {"fetch": 0.50002, "write": 1.0}    # counter KiB per KiB moved by the 1 GiB copy
+
+
+def kernel_source_hash(kernel):
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[kernel]:
+        with open(os.path.join(ROOT, "paper_2506_19139_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, args):
+    c = COUNTERS.get(kernel)
+    default = (args.n, args.tile, args.window) == (1_000_000, 16, 8)
+    if not c or not default or None in COUNTER_SCALE.values() or c["src"] != kernel_source_hash(kernel):
+        return None
+    return round((c["fetch_kib"] / COUNTER_SCALE["fetch"] + c["write_kib"] / COUNTER_SCALE["write"]) * 1024)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -153,10 +185,11 @@ def main():
     grads = dict(means=torch.empty_like(g.means), scales=torch.empty_like(g.scales), quats=torch.empty_like(g.quats),
                  opac=torch.empty_like(g.opac), sh=torch.empty_like(g.sh))
     stream = torch.cuda.current_stream()
-    ev = {k: [] for k in ("project", "bin_sort", "render_fwd", "render_bwd")}
+    ev = {k: [] for k in ("project", "bin_sort", "render_fwd_call", "render_bwd_call")}
+    timer = sof.KernelTimer()
 
     def step(record):
-        marks = [torch.cuda.Event(enable_timing=True) for _ in range(5)] if record else None
+        marks = [torch.cuda.Event(enable_timing=True) for _ in range(6)] if record else None
         if record: marks[0].record(stream)
         sof.project(g, C, opts, rast.proj)
         if record: marks[1].record(stream)
@@ -166,14 +199,12 @@ def main():
                        out["aux"])
         if record: marks[3].record(stream)
         d_rgb = torch.sign(out["rgb"] - target) * (1.0 / out["rgb"].numel())       # L1 loss gradient
-        m = torch.cuda.Event(enable_timing=True) if record else None
-        if record: m.record(stream)
-        rast.backward(g, out, d_rgb, d_acc, d_depth, d_normal, grads_out=grads)
         if record: marks[4].record(stream)
+        rast.backward(g, out, d_rgb, d_acc, d_depth, d_normal, grads_out=grads)
+        if record: marks[5].record(stream)
         if record:
-            for k, (a, b) in zip(("project", "bin_sort", "render_fwd"), zip(marks[:3], marks[1:4])):
-                ev[k].append((a, b))
-            ev["render_bwd"].append((m, marks[4]))
+            for k, (a, b) in zip(ev, ((0, 1), (1, 2), (2, 3), (4, 5))):
+                ev[k].append((marks[a], marks[b]))
 
     log("warmup")
     for _ in range(args.warmup):
@@ -185,10 +216,13 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        step(True)
+        with timer:                        # HIP events around the two rasteriser kernels
+            step(True)
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) / args.steps * 1e3
     per = {k: float(np.mean([a.elapsed_time(b) for a, b in v])) for k, v in ev.items()}
+    kern = {k: float(np.mean(timer.ms(k))) for k in ("render_fwd", "render_bwd")}
+    per["k_render_fwd"], per["k_render_bwd"] = kern["render_fwd"], kern["render_bwd"]
 
     aux = out["aux"].view(sof.AUX_CHANNELS, P)
     n_emit = aux[1].view(torch.int32).double().sum().item()
@@ -196,12 +230,15 @@ def main():
     cands = aux[5].view(torch.int32).double().sum().item()
     fwd_flops = FLOP_EVAL * walked + FLOP_CAND * cands + FLOP_BLEND * n_emit
     bwd_flops = FLOP_EVAL * walked + FLOP_CAND * cands + FLOP_ADJ * n_emit
-    dominant = "render_bwd" if per["render_bwd"] >= per["render_fwd"] else "render_fwd"
+    dominant = "render_bwd" if kern["render_bwd"] >= kern["render_fwd"] else "render_fwd"
     flops = bwd_flops if dominant == "render_bwd" else fwd_flops
-    achieved = flops / (per[dominant] * 1e-3) / 1e12
-    roofline = {"bound": "alu", "kernel": dominant, "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4), "traffic": None,
-                "work": {"entries_tested": int(walked), "candidates": int(cands), "blended": int(n_emit)}}
+    achieved = flops / (kern[dominant] * 1e-3) / 1e12
+    roofline = {"bound": "alu", "kernel": f"k_{dominant}", "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
+                "traffic": measured_traffic(f"k_{dominant}", args),
+                "kernel_ms": round(kern[dominant], 4),
+                "work": {"entries_tested": int(walked), "candidates": int(cands), "blended": int(n_emit),
+                         "flop": int(flops)}}
 
     result = {
         "metric": METRIC,
@@ -238,18 +275,22 @@ def main():
         q.auto_capacity = False
         torch.cuda.synchronize()
         times = []
+        qtimer = sof.KernelTimer()
         for _ in range(args.query_steps):
             a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            a.record(stream)
-            q(qg, pts, out=o)
-            b.record(stream)
+            with qtimer:
+                a.record(stream)
+                q(qg, pts, out=o)
+                b.record(stream)
             torch.cuda.synchronize()
             times.append(a.elapsed_time(b))
         tq = float(np.median(times))
+        tk = float(np.median(qtimer.ms("query")))
         npts = int(pts.shape[0])
         result["query"] = {"workload": f"{args.query_gaussians} Gaussians, {npts} points (centres + 3-sigma box "
                                        f"corners), min over {len(qcams)} views 960x540, one persistent launch",
-                           "ms": round(tq, 2), "points_per_s": round(npts / (tq * 1e-3), 1),
+                           "ms": round(tq, 2), "eval_kernel_ms": round(tk, 2),
+                           "points_per_s": round(npts / (tq * 1e-3), 1),
                            "point_views_per_s": round(q.last[1] / (tq * 1e-3), 1),
                            "point_view_pairs": int(q.last[1]), "instances": int(q.last[0])}
         del q, qg, pts, o

@@ -206,6 +206,18 @@ int sof_opacity_query(const sof_gaussians* g, const sof_camera* h_cams, const so
                       int64_t pv_capacity, float* opacity, void* proj, size_t proj_bytes, void* bins,
                       size_t bins_bytes, void* sched, size_t sched_bytes, hipStream_t stream);
 
+/*
+ * Instrumentation, not part of the method: per-kernel timing for benchmarks.  `events`
+ * points to 6 hipEvent_t handles created by the caller (or is NULL to switch timing off);
+ * while set, every later call records, on its own stream, events[0]/[1] immediately before
+ * and after the sof_render_fwd kernel, events[2]/[3] around the rasteriser adjoint kernel
+ * of sof_render_bwd (the per-Gaussian reduction that follows it is excluded) and
+ * events[4]/[5] around the evaluation kernel of sof_opacity_query.  A NULL handle skips
+ * that record.  The handles are borrowed, not owned; the setting is process-wide and not
+ * thread-safe.  Always returns SOF_OK.
+ */
+int sof_set_timing_events(void* const* events);
+
 /* Human-readable text for a sof_status value (static storage). */
 const char* sof_strerror(int code);
 

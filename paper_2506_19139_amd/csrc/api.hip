@@ -52,11 +52,25 @@ int hip_status(hipError_t e) { return e == hipSuccess ? SOF_OK : SOF_E_HIP; }
 
 int sorted_parity(int64_t n_tiles) { return (((32 + bits_for(n_tiles)) + 7) / 8) & 1; }
 
+hipEvent_t g_timing[2 * kTimedKernels] = {};
+
 }  // namespace
+
+namespace sof {
+void timing_mark(TimedKernel k, int end, hipStream_t s) {
+  hipEvent_t ev = g_timing[2 * (int)k + end];
+  if (ev) hipEventRecord(ev, s);
+}
+}  // namespace sof
 
 extern "C" {
 
 size_t sof_read_status_offset(void) { return 0; }
+
+int sof_set_timing_events(void* const* events) {
+  for (int k = 0; k < 2 * kTimedKernels; ++k) g_timing[k] = events ? (hipEvent_t)events[k] : nullptr;
+  return SOF_OK;
+}
 
 const char* sof_strerror(int code) {
   switch (code) {
@@ -161,7 +175,10 @@ int sof_render_fwd(int64_t n, const sof_camera* h_cams, const sof_camera* d_cams
   a.rgb = rgb; a.acc = acc; a.depth = depth; a.normal = normal; a.aux = aux;
   if (trace_enabled())
     fprintf(stderr, "[sof] render_fwd tiles=%lld tile=%d window=%d\n", (long long)n_tiles, opts->tile, opts->window);
-  return hip_status(launch_render_fwd(a, opts->tile, opts->window, n_tiles, stream));
+  timing_mark(kTimeRenderFwd, 0, stream);
+  const hipError_t e = launch_render_fwd(a, opts->tile, opts->window, n_tiles, stream);
+  timing_mark(kTimeRenderFwd, 1, stream);
+  return hip_status(e);
 }
 
 int sof_render_bwd(const sof_gaussians* g, const sof_camera* h_cams, const sof_camera* d_cams, int32_t n_cams,
@@ -191,7 +208,9 @@ int sof_render_bwd(const sof_gaussians* g, const sof_camera* h_cams, const sof_c
   b.f.aux = (float*)aux;
   if (trace_enabled())
     fprintf(stderr, "[sof] render_bwd tiles=%lld tile=%d window=%d\n", (long long)n_tiles, opts->tile, opts->window);
+  timing_mark(kTimeRenderBwd, 0, stream);
   hipError_t e = launch_render_bwd(b, opts->tile, opts->window, n_tiles, stream);
+  timing_mark(kTimeRenderBwd, 1, stream);
   if (e != hipSuccess) return SOF_E_HIP;
   ProjectBwdArgs pa;
   pa.means = g->means; pa.scales = g->scales; pa.quats = g->quats; pa.opac = g->opacities; pa.sh = g->sh;

@@ -82,4 +82,8 @@ struct ProjectBwdArgs {
 };
 hipError_t launch_project_bwd(const ProjectBwdArgs& a, hipStream_t s);
 
+// Optional timing events recorded around single kernels (see sof_set_timing_events).
+enum TimedKernel { kTimeRenderFwd = 0, kTimeRenderBwd = 1, kTimeQuery = 2, kTimedKernels = 3 };
+void timing_mark(TimedKernel k, int end, hipStream_t s);
+
 }  // namespace sof

@@ -413,8 +413,11 @@ int sof_opacity_query(const sof_gaussians* g, const sof_camera* h_cams, const so
   hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_query_eval, kQueryBlock, 0);
   const int64_t grid = (int64_t)(cus > 0 ? cus : 256) * (per_cu > 0 ? per_cu : 1);
   const int64_t maxb = S.max_blocks;
+  timing_mark(kTimeQuery, 0, s);
   hipLaunchKernelGGL(k_query_eval, dim3((unsigned)(grid < maxb ? grid : maxb)), dim3(kQueryBlock), 0, s, qa);
-  return hipGetLastError() == hipSuccess ? SOF_OK : SOF_E_HIP;
+  const hipError_t le = hipGetLastError();
+  timing_mark(kTimeQuery, 1, s);
+  return le == hipSuccess ? SOF_OK : SOF_E_HIP;
 }
 
 }  // extern "C"

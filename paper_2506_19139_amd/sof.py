@@ -69,6 +69,7 @@ _SIGS = {
                                                 ctypes.c_int64, _SZ, _SZ, _SZ]),
     "sof_opacity_query": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, _P, _P, ctypes.c_int64, ctypes.c_int64,
                                          _P, _P, ctypes.c_size_t, _P, ctypes.c_size_t, _P, ctypes.c_size_t, _P]),
+    "sof_set_timing_events": (ctypes.c_int, [_P]),
     "sof_strerror": (ctypes.c_char_p, [ctypes.c_int]),
 }
 
@@ -233,6 +234,38 @@ def read_status(buf: torch.Tensor):
     off = lib().sof_read_status_offset()
     raw = buf[off:off + 16].cpu().numpy()
     return int(raw[:8].view(np.int64)[0]), int(raw[8:12].view(np.int32)[0])
+
+
+TIMED_KERNELS = ("render_fwd", "render_bwd", "query")
+
+
+class KernelTimer:
+    """HIP events recorded by the library immediately around its rasteriser and query
+    kernels (sof_set_timing_events), for per-kernel durations on the launch stream.  Usage:
+    `with timer: <calls>` then `timer.ms("render_bwd")` after a synchronisation.  Each use
+    of the context holds one fresh set of events."""
+
+    def __init__(self):
+        self.sets = []
+
+    def __enter__(self):
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(2 * len(TIMED_KERNELS))]
+        for e in evs:
+            e.record()                        # creates the underlying hipEvent
+        torch.cuda.synchronize()
+        handles = (ctypes.c_void_p * len(evs))(*[e.cuda_event for e in evs])
+        _check(lib().sof_set_timing_events(handles), "sof_set_timing_events")
+        self.sets.append(evs)
+        return self
+
+    def __exit__(self, *exc):
+        lib().sof_set_timing_events(None)
+        return False
+
+    def ms(self, kernel):
+        """Per-use durations (ms) of `kernel`, one entry per context use."""
+        k = TIMED_KERNELS.index(kernel)
+        return [evs[2 * k].elapsed_time(evs[2 * k + 1]) for evs in self.sets]
 
 
 # ------------------------------------------------------------------------------ views of bins
