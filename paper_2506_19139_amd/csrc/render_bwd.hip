@@ -28,6 +28,42 @@ struct PixBwd {
   bool done, crossed;
 };
 
+// Cross-lane read inside a row of 16 lanes (DPP, no LDS round trip).
+constexpr int kDppRowMirror = 0x140;       // lane i reads lane 15 - i of its row
+constexpr int kDppRowHalfMirror = 0x141;   // lane i reads lane 7 - i of its half-row (i ^ 7)
+constexpr int kDppQuadXor2 = 0x4E;         // quad permutation (2, 3, 0, 1)
+constexpr int kDppQuadXor1 = 0xB1;         // quad permutation (1, 0, 3, 2)
+template <int CTRL>
+__device__ inline float dpp_pull(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+
+// Sum over the lanes where `mine` holds of 16 per-lane fields; every lane of the wave must be
+// active.  Inside each 16-lane row a reduce-scatter over four DPP stages halves the fields a
+// lane carries (the partner of each stage differs in one bit of the lane index: 3, 2, 1, 0),
+// leaving lane i with the row's total of field i; two cross-row exchanges then add the four
+// rows.  On return lane l holds the wave total of field (l & 15).
+__device__ inline float wave_field_sums16(const float* gv, bool mine, int lane) {
+  const int i = lane & 15;
+  const bool b3 = (i & 8) != 0, b2 = (i & 4) != 0, b1 = (i & 2) != 0, b0 = (i & 1) != 0;
+  float v8[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const float lo = mine ? gv[k] : 0.f, hi = mine ? gv[k + 8] : 0.f;
+    v8[k] = (b3 ? hi : lo) + dpp_pull<kDppRowMirror>(b3 ? lo : hi);
+  }
+  float v4[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) v4[k] = (b2 ? v8[k + 4] : v8[k]) + dpp_pull<kDppRowHalfMirror>(b2 ? v8[k] : v8[k + 4]);
+  float v2[2];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) v2[k] = (b1 ? v4[k + 2] : v4[k]) + dpp_pull<kDppQuadXor2>(b1 ? v4[k] : v4[k + 2]);
+  float v1 = (b0 ? v2[1] : v2[0]) + dpp_pull<kDppQuadXor1>(b0 ? v2[0] : v2[1]);
+  v1 += __shfl_xor(v1, 16);
+  v1 += __shfl_xor(v1, 32);
+  return v1;
+}
+
 template <int TS, int W>
 __global__ __launch_bounds__(TS * TS) void k_render_bwd(RenderBwdArgs A) {
   constexpr int NT = TS * TS;
@@ -230,7 +266,7 @@ __global__ __launch_bounds__(TS * TS) void k_render_bwd(RenderBwdArgs A) {
   // wave-cooperatively.  Lanes of one wave often hold the same instance (neighbouring
   // pixels share Gaussians), and float atomics to one LDS address serialise, so lanes are
   // grouped by instance: small groups add directly, a larger group is first summed across
-  // the wave with a reduce-scatter (each of 16 lanes ends with one field's total) and adds
+  // the wave (wave_field_sums16: each of 16 lanes ends with one field's total) and adds
   // once.  Entries older than the two resident batches add to the global buffer.
   auto round = [&](int cur_b) {
     float gv[kGradFields];
@@ -272,34 +308,8 @@ __global__ __launch_bounds__(TS * TS) void k_render_bwd(RenderBwdArgs A) {
       const uint64_t m = __ballot(resident && pos == lp) & big;
       big &= ~m;
       const bool mine = (m >> lane) & 1ull;
-      // reduce-scatter over lane bits 5..2: 16 fields -> 1 field per lane
-      float v8[8];
-      const bool b5 = (lane >> 5) & 1, b4 = (lane >> 4) & 1, b3 = (lane >> 3) & 1, b2 = (lane >> 2) & 1;
-#pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        const float lo = mine ? gv[k] : 0.f, hi = mine ? gv[k + 8] : 0.f;
-        const float recv = __shfl_xor(b5 ? lo : hi, 32);
-        v8[k] = (b5 ? hi : lo) + recv;
-      }
-      float v4[4];
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const float recv = __shfl_xor(b4 ? v8[k] : v8[k + 4], 16);
-        v4[k] = (b4 ? v8[k + 4] : v8[k]) + recv;
-      }
-      float v2[2];
-#pragma unroll
-      for (int k = 0; k < 2; ++k) {
-        const float recv = __shfl_xor(b3 ? v4[k] : v4[k + 2], 8);
-        v2[k] = (b3 ? v4[k + 2] : v4[k]) + recv;
-      }
-      float v1 = (b2 ? v2[1] : v2[0]) + __shfl_xor(b2 ? v2[0] : v2[1], 4);
-      v1 += __shfl_xor(v1, 2);
-      v1 += __shfl_xor(v1, 1);
-      if ((lane & 3) == 0) {
-        const int field = (b5 ? 8 : 0) + (b4 ? 4 : 0) + (b3 ? 2 : 0) + (b2 ? 1 : 0);
-        atomicAdd(&gsl[((int)lp % NS) * kSlotStride + field], v1);
-      }
+      const float v = wave_field_sums16(gv, mine, lane);
+      if (lane < kGradFields) atomicAdd(&gsl[((int)lp % NS) * kSlotStride + lane], v);
     }
     has = false;
   };
