@@ -344,7 +344,11 @@ __global__ __launch_bounds__(TS * TS) void k_render_bwd(RenderBwdArgs A) {
       ring_e[(i - rg.x) % NS] = e;
       ring_g[(i - rg.x) % NS] = g;
     }
-    __threadfence();
+    // The flushed slots and any later global atomics on them (entries emitted after their
+    // batch left the ring) come from this workgroup only: waiting until this lane's stores
+    // are acknowledged by L2 and then the barrier order them, without the L2 write-back and
+    // invalidation of a device-scope fence.
+    __builtin_amdgcn_s_waitcnt(0x0F70);                 // vmcnt(0)
     __syncthreads();
     const int nb = min(B, rg.y - bs);
     for (int j = 0; j < nb; ++j) {
