@@ -79,7 +79,12 @@ def parse():
     ap.add_argument("--query-gaussians", type=int, default=3_000_000)
     ap.add_argument("--query-steps", type=int, default=2)
     ap.add_argument("--no-query", action="store_true")
+    ap.add_argument("--query-tile", type=int, default=8)
+    ap.add_argument("--no-per-view", action="store_true",
+                    help="skip the comparison against one query launch per view")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-multiview", action="store_true",
+                    help="skip the 8-camera graph-captured training step")
     ap.add_argument("--cpu-pixels", type=int, default=160)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one device copy of this many MiB first (scale reference for HBM byte counters)")
@@ -140,6 +145,67 @@ def cpu_baseline(scene, cam, window, n_pixels, stride=10):
                   f"no backward (the oracle's gradient is finite differences)",
         "pixels_per_s_full_scene": round(px_per_s_full, 4),
     }
+
+
+def per_view_query(qg, pts, qcams, tile, batched, t_batched, stream):
+    """The same query as one launch per view: 96 single-camera calls (buffers sized by an
+    untimed pass, then fixed), each followed by a running minimum on the device."""
+    import torch
+    from paper_2506_19139_amd import sof
+    views = [sof.Cameras([c]) for c in qcams.list]
+    q = sof.OpacityQuery(views[0], sof.Options(tile=tile))
+    out = torch.empty_like(batched)
+    acc = torch.empty_like(batched)
+    for v in views:                                   # sizing pass (host read-backs)
+        q.cams = v
+        q(qg, pts, out=out)
+    q.auto_capacity = False
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    acc.fill_(1.0)
+    for v in views:
+        q.cams = v
+        q(qg, pts, out=out)
+        torch.minimum(acc, out, out=acc)
+    b.record(stream)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b)
+    diff = (acc - batched).abs().max().item()
+    return {"ms": round(ms, 2), "points_per_s": round(pts.shape[0] / (ms * 1e-3), 1),
+            "batched_speedup": round(ms / t_batched, 3), "max_abs_diff_vs_batched": diff}
+
+
+def multiview_step(g, stream, reps=10):
+    """Eight cameras of uneven resolution (640x360 .. 1920x1080) in one training step: the
+    tile size (and, separately, the window) picked by the autotuner, then the whole step
+    (project, bin_sort, render_fwd, L1 gradient, render_bwd) captured in one HIP graph."""
+    import torch
+    from paper_2506_19139_amd import scenes, sof, step
+    cams = sof.Cameras(scenes.multiview_cameras())
+    target = torch.from_numpy(np.concatenate([scenes.target_image(h, w, seed=1 + k).reshape(-1)
+                                              for k, (w, h) in enumerate(scenes.MULTIVIEW_SIZES)])).cuda()
+    tile8 = step.autotune(g, cams, target, window=8, tiles=(8, 16, 32), cache_path=None)
+    full = step.autotune(g, cams, target, window=8, tiles=(8, 16, 32), windows=(4, 8, 16), cache_path=None)
+    st = step.TrainStep(g, cams, sof.Options(tile=tile8[0], window=8), target).capture()
+    for _ in range(2):
+        st.replay()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(reps):
+        st.replay()
+    b.record(stream)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    k_used, flags = st.status()
+    assert flags == 0, "instance capacity exceeded in the captured step"
+    return {"workload": f"{g.n} Gaussians, 8 cameras " + ", ".join(f"{w}x{h}" for w, h in scenes.MULTIVIEW_SIZES)
+                        + f" ({cams.n_pixels / 1e6:.2f} Mpx), fwd+bwd, L1, one HIP graph",
+            "window": 8, "tile": tile8[0], "graph_ms": round(ms, 3),
+            "mpx_per_s": round(cams.n_pixels / (ms * 1e-3) / 1e6, 1), "instances": int(k_used),
+            "tuner_window8_ms": round(tile8[2], 3),
+            "tuner_over_tile_and_window": {"tile": full[0], "window": full[1], "ms": round(full[2], 3)}}
 
 
 # --------------------------------------------------------------------------- GPU
@@ -260,6 +326,11 @@ def main():
         "roofline": roofline,
     }
 
+    if not args.no_multiview:
+        log("multiview step")
+        result["multiview"] = multiview_step(g, stream)
+        torch.cuda.empty_cache()
+
     if not args.no_query:
         log("query workload")
         del rast, out, grads
@@ -270,7 +341,7 @@ def main():
         qg = sof.Gaussians.from_numpy(qscene)
         pts = torch.from_numpy(pts_np).cuda()
         del pts_np
-        q = sof.OpacityQuery(qcams, sof.Options(tile=16))
+        q = sof.OpacityQuery(qcams, sof.Options(tile=args.query_tile))
         o = q(qg, pts)                                  # sizes the buffers (host read-back)
         q.auto_capacity = False
         torch.cuda.synchronize()
@@ -293,6 +364,9 @@ def main():
                            "points_per_s": round(npts / (tq * 1e-3), 1),
                            "point_views_per_s": round(q.last[1] / (tq * 1e-3), 1),
                            "point_view_pairs": int(q.last[1]), "instances": int(q.last[0])}
+        if not args.no_per_view:
+            log("query, one launch per view")
+            result["query"]["per_view_launches"] = per_view_query(qg, pts, qcams, args.query_tile, o, tq, stream)
         del q, qg, pts, o
         torch.cuda.empty_cache()
 
