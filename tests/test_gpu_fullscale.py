@@ -1,0 +1,297 @@
+"""Parity at the full sizes of the benchmark workloads, on sampled outputs.
+
+The HIP path runs on the whole scene, launched as the benchmark launches it; the float64
+oracle evaluates sampled pixels (or points) only.  To keep its brute force tractable the
+oracle runs on the sub-scene of Gaussians that can reach the sampled rays at all: if
+o G(x) >= a somewhere on a ray, the ray crosses the ellipsoid (x - mu)^T Sigma^-1 (x - mu)
+<= 2 ln(o / a), so it passes within sqrt(2 ln(o / a)) max(s) of the mean.  With
+a = 1 / (2 * 255), half the candidate cut, the sub-scene holds every Gaussian that is a
+candidate (alpha >= 1/255) for a sampled ray at the inputs and at every perturbation used by
+the directional finite differences below (relative size 1e-6), so per-ray oracle results on
+it equal those on the whole scene.  Sub-scenes keep increasing original indices, so the
+level-0 order (float32 view depth, index) breaks ties the same way; crossing ids reported by
+the oracle are mapped back to whole-scene ids before comparison.  For the point query the
+ray is the segment from each camera centre to the point.
+
+Gradients: the upstream gradient is a random linear functional of (rgb, acc, depth, normal)
+on the sampled pixels and zero elsewhere, so the HIP backward of the whole scene and the
+oracle's loss on the sub-scene describe the same function; its directional derivative along
+random directions (every parameter of the sub-scene, scaled by max(1, |theta|), scales by
+|s|) is compared with a central difference of the oracle (h = 1e-6); directions whose two
+evaluations differ in emitted order, crossing or any used Gaussian's normal are redrawn.  The depth output is the exact depth with
+a detached correction (the default), whose gradient is that of the median depth t*_k."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_helpers import TOL_ABS, compare_images, unpack
+from oracle import sof_oracle as O
+from paper_2506_19139_amd import scenes, sof
+
+pytestmark = pytest.mark.gpu
+
+ALPHA_FLOOR = 0.5 / 255.0
+PARAMS = ("means", "scales", "quats", "opac", "sh")
+GPU_KEY = {"means": "means", "scales": "scales", "quats": "quats", "opac": "opac", "sh": "sh"}
+
+
+def _reach(scene, a=ALPHA_FLOOR):
+    o = scene["opac"].astype(np.float64)
+    r = np.sqrt(2.0 * np.log(np.maximum(o / a, 1.0))) * scene["scales"].astype(np.float64).max(axis=1)
+    return r * (1.0 + 1e-3)
+
+
+def _ray_superset(scene, cam, pixels, reach):
+    """Indices of Gaussians whose reach sphere meets any of the pixel rays (whole lines)."""
+    oc = O.Camera.from_arrays(**cam)
+    mu = scene["means"].astype(np.float64)
+    rel = mu - oc.center[None, :]
+    keep = np.zeros(len(mu), bool)
+    for px, py in pixels:
+        d, _ = oc.pixel_ray(px, py)
+        t = rel @ d
+        dist2 = np.einsum("ij,ij->i", rel, rel) - t * t
+        keep |= dist2 <= reach * reach
+    return keep
+
+
+def _segment_superset(scene, cams, x, reach):
+    """Indices of Gaussians whose reach sphere meets a segment from a camera centre to x."""
+    mu = scene["means"].astype(np.float64)
+    keep = np.zeros(len(mu), bool)
+    x = np.asarray(x, np.float64)
+    for cam in cams:
+        c = O.Camera.from_arrays(**cam).center
+        rel = mu - c[None, :]
+        seg = x - c
+        L = float(np.linalg.norm(seg))
+        p = rel @ (seg / L)
+        t = np.clip(p, 0.0, L)
+        dist2 = np.einsum("ij,ij->i", rel, rel) - 2.0 * t * p + t * t
+        keep |= dist2 <= reach * reach
+    return np.nonzero(keep)[0]
+
+
+def _sample_pixels(cam, n, seed):
+    rng = np.random.default_rng(seed)
+    return [(int(x), int(y)) for x, y in zip(rng.integers(0, cam["width"], n), rng.integers(0, cam["height"], n))]
+
+
+def _forward_parity(cams, pixels_per_cam, host, cam_ids, scene, window):
+    """Compare the sampled pixels of every camera with the oracle on that camera's
+    sub-scene."""
+    totals = [0, 0, 0]
+    for ci, (cam, pixels, ids) in enumerate(zip(cams, pixels_per_cam, cam_ids)):
+        gpu = unpack(host, cams, ci)
+        sc = O.Scene.from_arrays(**scenes.subset_scene(scene, ids))
+        oc = O.Camera.from_arrays(**cam)
+        v = O.view(sc, oc)
+        orc = O.render(sc, oc, window, pixels=pixels)
+        k = np.asarray(orc["k"])
+        orc["k"] = np.where(k >= 0, ids[np.maximum(k, 0)], -1)
+        bad, unflagged, frag, worst = compare_images(gpu, orc, sc, v, pixels)
+        totals[0] += bad
+        totals[1] += unflagged
+        totals[2] += frag
+        print(f"  camera {ci} {cam['width']}x{cam['height']}: {len(ids)} Gaussians, mismatching {bad} "
+              f"fragile {frag} worst {worst}")
+    return totals
+
+
+def _directional_fd(scene, cams, pixels_per_cam, weights, cam_ids, grads, window, n_dirs=3, seed=0, h=1e-6):
+    """Directional derivatives of the oracle's loss (summed over cameras, each evaluated on
+    its own sub-scene) against the HIP gradient; returns (hip, fd, groups) for directions
+    whose two evaluations lie in the same smooth piece."""
+    sub_ids = np.unique(np.concatenate(cam_ids))
+    sub = scenes.subset_scene(scene, sub_ids)
+    base = {k: sub[k].astype(np.float64) for k in PARAMS}
+    local = [np.searchsorted(sub_ids, ids) for ids in cam_ids]
+    ocams = [O.Camera.from_arrays(**c) for c in cams]
+    rng = np.random.default_rng(seed)
+    out = []
+    tries = 0
+    while len(out) < n_dirs and tries < 3 * n_dirs:
+        tries += 1
+        # direction: all parameters, geometry only, or appearance only
+        groups = [PARAMS, ("means", "scales", "quats"), ("opac", "sh")][len(out) % 3]
+        # scales move relative to themselves, so that near-equal axes of a Gaussian rarely swap
+        dirs = {k: (rng.normal(0.0, 1.0, base[k].shape) * (np.abs(base[k]) if k == "scales"
+                                                            else np.maximum(1.0, np.abs(base[k])))
+                    if k in groups else np.zeros(base[k].shape)) for k in PARAMS}
+
+        def loss(sign):
+            total, sigs = 0.0, []
+            for oc, loc, pix, wts in zip(ocams, local, pixels_per_cam, weights):
+                arr = {k: (base[k] + sign * h * dirs[k])[loc] for k in PARAMS}
+                sc = O.Scene(arr["means"], arr["scales"], arr["quats"], arr["opac"].reshape(-1), arr["sh"],
+                             int(sub["sh_degree"]))
+                lo, sig = O.linear_loss(sc, [oc], window, [pix], [wts], depth_mode="median")
+                # the per-Gaussian normal (shortest axis, flipped to face the camera) is piecewise
+                # constant in the parameters: its jumps are discontinuities the order misses
+                used = sorted({int(i) for order, _ in sig for i in order})
+                total += lo
+                sigs.append((sig, O.gaussian_normals(O.Scene(arr["means"][used], arr["scales"][used],
+                                                             arr["quats"][used], arr["opac"][used].reshape(-1),
+                                                             arr["sh"][used], int(sub["sh_degree"])), oc.center)))
+            return total, sigs
+
+        lp, sp = loss(+1.0)
+        lm, sm = loss(-1.0)
+        smooth = all(a[0] == b[0] and np.abs(a[1] - b[1]).max(initial=0.0) <= 1e-3 for a, b in zip(sp, sm))
+        if not smooth:
+            print("  direction crosses a discontinuity; drawn again")
+            continue
+        fd = (lp - lm) / (2.0 * h)
+        g = sum(float(np.sum(grads[GPU_KEY[k]][sub_ids].astype(np.float64).reshape(dirs[k].shape) * dirs[k]))
+                for k in PARAMS)
+        out.append((g, fd, groups))
+    return out
+
+
+def _upstream(cams, pixels_per_cam, seed):
+    """Random weights on the sampled pixels: oracle layout [n, 8] per camera and the
+    concatenated planar upstream buffers of the HIP path."""
+    rng = np.random.default_rng(seed)
+    P = sum(c["width"] * c["height"] for c in cams)
+    d_rgb = np.zeros(3 * P, np.float32)
+    d_acc = np.zeros(P, np.float32)
+    d_depth = np.zeros(P, np.float32)
+    d_nrm = np.zeros(3 * P, np.float32)
+    weights = []
+    off = 0
+    for cam, pixels in zip(cams, pixels_per_cam):
+        hw = cam["width"] * cam["height"]
+        w = rng.normal(0.0, 1.0, (len(pixels), 8)).astype(np.float32)
+        w[:, 4] *= 0.1                                       # depth is in metres
+        weights.append(w.astype(np.float64))
+        for (px, py), row in zip(pixels, w):
+            i = py * cam["width"] + px
+            for ch in range(3):
+                d_rgb[3 * off + ch * hw + i] += row[ch]
+                d_nrm[3 * off + ch * hw + i] += row[5 + ch]
+            d_acc[off + i] += row[3]
+            d_depth[off + i] += row[4]
+        off += hw
+    dev = lambda a: torch.from_numpy(a).cuda()
+    return weights, dev(d_rgb), dev(d_acc), dev(d_depth), dev(d_nrm)
+
+
+def _check_directions(pairs, what):
+    assert pairs, f"{what}: no smooth direction found"
+    for g, fd, groups in pairs:
+        rel = abs(g - fd) / max(abs(fd), 1e-30)
+        print(f"  {what} {'/'.join(groups)}: hip {g:.9e} fd {fd:.9e} rel {rel:.2e}")
+        assert rel <= 1e-3, (what, groups, g, fd, rel)
+
+
+def _run_training_case(scene, cams, tile, window, pixels_per_cam, seed, label):
+    r = sof.Rasterizer(sof.Cameras(cams), sof.Options(tile=tile, window=window))
+    g = sof.Gaussians.from_numpy(scene)
+    out = r.forward(g)
+    torch.cuda.synchronize()
+    host = {k: v.cpu().numpy() for k, v in out.items()}
+    reach = _reach(scene)
+    cam_ids = [np.nonzero(_ray_superset(scene, cam, pixels, reach))[0] for cam, pixels in zip(cams, pixels_per_cam)]
+    print(f"[case] {label}: {sum(map(len, cam_ids))} (camera, Gaussian) pairs reach the "
+          f"{sum(map(len, pixels_per_cam))} sampled rays", flush=True)
+    bad, unflagged, frag = _forward_parity(cams, pixels_per_cam, host, cam_ids, scene, window)
+    assert unflagged == 0, (label, bad, frag)
+    weights, d_rgb, d_acc, d_depth, d_nrm = _upstream(cams, pixels_per_cam, seed)
+    grads = r.backward(g, out, d_rgb, d_acc, d_depth, d_nrm)
+    torch.cuda.synchronize()
+    grads = {k: v.cpu().numpy() for k, v in grads.items()}
+    outside = np.ones(len(scene["opac"]), bool)
+    outside[np.concatenate(cam_ids)] = False
+    for k, v in grads.items():                   # no sampled ray reaches these Gaussians
+        assert float(np.abs(v[outside]).max(initial=0.0)) == 0.0, k
+    pairs = _directional_fd(scene, cams, pixels_per_cam, weights, cam_ids, grads, window, seed=seed)
+    _check_directions(pairs, label)
+
+
+@pytest.fixture(scope="module")
+def unbounded_1m():
+    return scenes.unbounded_scene(1_000_000, seed=0)
+
+
+def test_unbounded_1m_1080p_training_step(unbounded_1m):
+    """1M Gaussians (unbounded recipe, SH 3), 1920x1080, tile 16, window 8: the benchmark's
+    headline launch.  64 sampled pixels: forward parity and three directional derivatives."""
+    cam = scenes.circle_camera(0.0, 1920, 1080)
+    _run_training_case(unbounded_1m, [cam], 16, 8, [_sample_pixels(cam, 64, 1)], 21, "unbounded 1M 1080p")
+
+
+def test_unbounded_1m_eight_cameras_training_step(unbounded_1m):
+    """The same scene through the eight uneven cameras (640x360 .. 1920x1080) in one call,
+    tile 8, window 16; 8 sampled pixels per camera."""
+    cams = scenes.multiview_cameras()
+    pix = [_sample_pixels(c, 8, 30 + i) for i, c in enumerate(cams)]
+    _run_training_case(unbounded_1m, cams, 8, 16, pix, 22, "unbounded 1M 8 cameras")
+
+
+def test_clusters_200k_720p_training_step():
+    """200k Gaussians in 50 anisotropic clusters, SH 3, 1280x720, tile 16, window 8."""
+    scene = scenes.cluster_scene()
+    cam = scenes.circle_camera(0.0, 1280, 720)
+    _run_training_case(scene, [cam], 16, 8, [_sample_pixels(cam, 64, 2)], 23, "clusters 200k 720p")
+
+
+def test_eight_camera_tiny_replica_full_fd():
+    """24 Gaussians seen by the eight camera shapes at 1/20 scale: every parameter against a
+    full central-difference gradient of the oracle (loss on 8 sampled pixels per camera)."""
+    scene = scenes.tiny_scene(n=24, seed=11, sh_degree=1, spread=1.5, log_scale=-0.7)
+    cams = scenes.multiview_cameras([(w // 20, h // 20) for w, h in scenes.MULTIVIEW_SIZES])
+    pix = []
+    for i, c in enumerate(cams):
+        pix.append(_sample_pixels(c, 8, 40 + i))
+    weights, d_rgb, d_acc, d_depth, d_nrm = _upstream(cams, pix, 24)
+    r = sof.Rasterizer(sof.Cameras(cams), sof.Options(tile=8, window=4))
+    g = sof.Gaussians.from_numpy(scene)
+    out = r.forward(g)
+    grads = r.backward(g, out, d_rgb, d_acc, d_depth, d_nrm)
+    torch.cuda.synchronize()
+    gpu = {k: v.cpu().numpy().astype(np.float64) for k, v in grads.items()}
+    print(f"[case] tiny replica, 8 cameras {[(c['width'], c['height']) for c in cams]}", flush=True)
+    sc = O.Scene.from_arrays(**scene)
+    ocams = [O.Camera.from_arrays(**c) for c in cams]
+    fd = O.fd_gradient(sc, ocams, 4, pix, weights, depth_mode="median")
+    for name in PARAMS:
+        ref, smooth = fd[name]
+        m = smooth.astype(bool)
+        got = gpu[GPU_KEY[name]].reshape(ref.shape)
+        rel = np.linalg.norm(got[m] - ref[m]) / max(np.linalg.norm(ref[m]), 1e-30)
+        print(f"  {name}: rel err {rel:.2e} over {m.sum()} entries ({int((~m).sum())} excluded)")
+        assert np.linalg.norm(ref[m]) > 0, name
+        assert rel <= 1e-3, (name, rel)
+
+
+def test_query_3m_27m_points_96_views_sampled():
+    """The benchmark's query: 3M Gaussians, 27M points (centres + 3-sigma box corners),
+    minimum over 96 cameras of 960x540, tile 8, one persistent launch; 6 sampled points (4 of them Gaussian centres)."""
+    scene = scenes.unbounded_scene(3_000_000, seed=0)
+    pts = scenes.box_corner_points(scene)
+    cams = scenes.ring_cameras(48, 960, 540)
+    print(f"[case] query 3M Gaussians {len(pts)} points 96 views", flush=True)
+    q = sof.OpacityQuery(sof.Cameras(cams), sof.Options(tile=8))
+    opacity = q(sof.Gaussians.from_numpy(scene), torch.from_numpy(pts).cuda())
+    torch.cuda.synchronize()
+    got = opacity.cpu().numpy()
+    rng = np.random.default_rng(5)
+    idx = np.concatenate([9 * rng.choice(len(pts) // 9, 4, replace=False), rng.choice(len(pts), 2, replace=False)])
+    reach = _reach(scene)
+    ocams = [O.Camera.from_arrays(**c) for c in cams]
+    for i in idx:
+        x = pts[i].astype(np.float64)
+        seen = [k for k, oc in enumerate(ocams) if O.point_view_valid(oc, x)]
+        # min over the views that see x of O_N(x), each view on its own sub-scene
+        ref, n_sub = 1.0, 0
+        for k in seen:
+            ids = _segment_superset(scene, [cams[k]], x, reach)
+            sc = O.Scene.from_arrays(**scenes.subset_scene(scene, ids))
+            ref = min(ref, O.opacity_field_view(sc, O.view(sc, ocams[k]), x))
+            n_sub += len(ids)
+        err = abs(float(got[i]) - ref)
+        print(f"  point {i}: seen by {len(seen)} views, {n_sub} (view, Gaussian) pairs reach it; "
+              f"hip {got[i]:.7f} oracle {ref:.7f} err {err:.1e}", flush=True)
+        assert err <= TOL_ABS, (i, got[i], ref)
