@@ -197,8 +197,10 @@ int sof_query_workspace_size(int64_t n, const sof_camera* h_cams, int32_t n_cams
  * t_eval = min(t*_i, |x - c_v|), counting Gaussians with alpha_i >= 1/255 whose evaluated
  * point lies beyond the near plane; 1 where no camera sees the point.  Points are scheduled
  * per (view, tile) in blocks of 256 sorted by depth (Eq. (14)); each tile's Gaussians are
- * sorted by z_min and the walk stops at z_min > z(x) (Eq. (15)) or once the partial O_N
- * already reaches the point's running minimum.  All (view, tile, block) work items run in
+ * sorted by a monotone key of z_min (32-bit keys quantise it to 1/128 octave when the tile
+ * ids fit in 20 bits, 64-bit keys keep it exact otherwise) and the walk stops once the key
+ * passes the point's own (Eq. (15); inside the point's bucket the exact z_min decides) or
+ * once the partial O_N already reaches the point's running minimum.  All (view, tile, block) work items run in
  * one persistent launch.  Overwrites opacity [n_points].
  */
 int sof_opacity_query(const sof_gaussians* g, const sof_camera* h_cams, const sof_camera* d_cams,

@@ -295,6 +295,41 @@ __global__ __launch_bounds__(256) void k_emit(const short4* rect, const float4* 
     }
 }
 
+// Query tile lists with 32-bit keys: (tile << dbits) | quantised z_min, value = Gaussian id.
+__global__ __launch_bounds__(256) void k_emit_query32(const short4* rect, const float* zmin, int64_t n, int64_t vn,
+                                                      int tile, const CamInfo* cams, const int32_t* counts,
+                                                      const int64_t* offsets, int64_t cap, int dbits, uint32_t* keys,
+                                                      uint32_t* vals, StatusBlock* status) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= vn) return;
+  const int cnt = counts[idx];
+  if (cnt == 0) return;
+  const short4 r = rect[idx];
+  const int c = (int)(idx / n);
+  const uint32_t g = (uint32_t)(idx - (int64_t)c * n);
+  const CamInfo ci = cams[c];
+  const uint32_t dk = query_depth_key(zmin[idx], query_key_shift(dbits));
+  int64_t e = offsets[idx];
+  if (e + cnt > cap) atomicOr(&status->flags, 1);
+  for (int ty = r.y / tile; ty <= r.w / tile; ++ty)
+    for (int tx = r.x / tile; tx <= r.z / tile; ++tx, ++e) {
+      if (e >= cap) return;
+      const uint32_t t = (uint32_t)(ci.tile_off + ty * ci.tiles_x + tx);
+      keys[e] = (t << dbits) | dk;
+      vals[e] = g;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_ranges32(const uint32_t* keys, const int64_t* count, int64_t cap, int dbits,
+                                                  int2* ranges) {
+  const int64_t n = live_count(count, cap);
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t t = keys[i] >> dbits;
+  if (i == 0 || (keys[i - 1] >> dbits) != t) ranges[t].x = (int)i;
+  if (i == n - 1 || (keys[i + 1] >> dbits) != t) ranges[t].y = (int)(i + 1);
+}
+
 __global__ __launch_bounds__(256) void k_fill_ranges(int2* ranges, int64_t n_tiles) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n_tiles) ranges[i] = make_int2(0, 0);
@@ -358,6 +393,55 @@ hipError_t launch_bin_sort(int64_t n, const sof_camera* d_cams, int n_cams, int6
   if (cap > 0) {
     hipLaunchKernelGGL(k_ranges, dim3((unsigned)div_up(cap, th)), dim3(th), 0, s, ks, &status->count, cap, ranges);
   }
+  return hipGetLastError();
+}
+
+int query_key_bits(int64_t n_tiles) {
+  const int tb = bits_for(n_tiles);
+  return tb <= 20 ? 32 - tb : 0;          // 0: tile ids too wide for 32-bit keys
+}
+
+hipError_t launch_query_bin_sort(int64_t n, const sof_camera* d_cams, int n_cams, int64_t n_tiles, int tile,
+                                 int64_t cap, const void* proj, void* bins, hipStream_t s, int* parity,
+                                 int* dbits_out) {
+  const int dbits = query_key_bits(n_tiles);
+  *dbits_out = dbits;
+  if (dbits == 0) return launch_bin_sort(n, d_cams, n_cams, n_tiles, tile, cap, 1, proj, bins, s, parity);
+  const int64_t vn = n * (int64_t)n_cams;
+  const ProjLayout P = ProjLayout::make(vn, true, n);
+  const BinsLayout B = BinsLayout::make(vn, n_cams, cap, n_tiles);
+  const char* pb = (const char*)proj;
+  char* bb = (char*)bins;
+  StatusBlock* status = (StatusBlock*)(bb + B.status);
+  CamInfo* cams = (CamInfo*)(bb + B.cams);
+  int32_t* counts = (int32_t*)(bb + B.counts);
+  int64_t* offsets = (int64_t*)(bb + B.offsets);
+  int64_t* scan_tmp = (int64_t*)(bb + B.scan_tmp);
+  uint32_t* k0 = (uint32_t*)(bb + B.keys0);
+  uint32_t* k1 = (uint32_t*)(bb + B.keys1);
+  uint32_t* v0 = (uint32_t*)(bb + B.vals0);
+  uint32_t* v1 = (uint32_t*)(bb + B.vals1);
+  int32_t* hist = (int32_t*)(bb + B.hist);
+  int32_t* hist_tmp = (int32_t*)(bb + B.hist_tmp);
+  int2* ranges = (int2*)(bb + B.ranges);
+  const short4* rect = (const short4*)(pb + P.rect);
+  const float* zmin = (const float*)(pb + P.zmin);
+
+  hipLaunchKernelGGL(k_cam_table, dim3(1), dim3(64), 0, s, d_cams, n_cams, tile, cams, status);
+  const int th = 256;
+  if (vn > 0) hipLaunchKernelGGL(k_count, dim3((unsigned)div_up(vn, th)), dim3(th), 0, s, rect, vn, tile, counts);
+  hipError_t e = exclusive_scan<int32_t, int64_t>(counts, vn, offsets, scan_tmp, &status->count, s);
+  if (e != hipSuccess) return e;
+  if (vn > 0)
+    hipLaunchKernelGGL(k_emit_query32, dim3((unsigned)div_up(vn, th)), dim3(th), 0, s, rect, zmin, n, vn, tile, cams,
+                       counts, offsets, cap, dbits, k0, v0, status);
+  e = radix_sort<uint32_t>(k0, v0, k1, v1, &status->count, cap, 32, hist, hist_tmp, parity, s);
+  if (e != hipSuccess) return e;
+  const uint32_t* ks = *parity ? k1 : k0;
+  hipLaunchKernelGGL(k_fill_ranges, dim3((unsigned)div_up(n_tiles > 0 ? n_tiles : 1, th)), dim3(th), 0, s, ranges, n_tiles);
+  if (cap > 0)
+    hipLaunchKernelGGL(k_ranges32, dim3((unsigned)div_up(cap, th)), dim3(th), 0, s, ks, &status->count, cap, dbits,
+                       ranges);
   return hipGetLastError();
 }
 

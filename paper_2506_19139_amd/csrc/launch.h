@@ -19,6 +19,12 @@ hipError_t launch_project(const sof_gaussians* g, const sof_camera* d_cams, int 
 hipError_t launch_bin_sort(int64_t n, const sof_camera* d_cams, int n_cams, int64_t n_tiles, int tile, int64_t cap,
                            int query_keys, const void* proj, void* bins, hipStream_t s, int* parity);
 // Per-camera tile / pixel offsets on the device (also resets the status block).
+// Tile lists for the opacity query: 32-bit keys (tile, quantised z_min) and Gaussian ids as
+// values when the tile ids fit in 20 bits (*dbits = depth-key bits), otherwise the 64-bit
+// lists of launch_bin_sort with exact z_min keys and emission indices (*dbits = 0).
+int query_key_bits(int64_t n_tiles);
+hipError_t launch_query_bin_sort(int64_t n, const sof_camera* d_cams, int n_cams, int64_t n_tiles, int tile,
+                                 int64_t cap, const void* proj, void* bins, hipStream_t s, int* parity, int* dbits);
 hipError_t launch_cam_table(const sof_camera* d_cams, int n_cams, int tile, CamInfo* out, StatusBlock* status,
                             hipStream_t s);
 

@@ -146,15 +146,16 @@ __global__ __launch_bounds__(256) void k_lut(const int32_t* nblk, const int32_t*
 }
 
 struct __align__(16) StageQ {
+  float zmin;           // the walk's skip test reads these four words in one 16-byte load
+  uint32_t qz;          // depth key of the list order (query_depth_key of zmin)
+  uint32_t rx, ry;      // pixel rectangle x0 | x1 << 16, y0 | y1 << 16
   int ui, vi;
   float uf, vf;
   float gx, gy, cxx, cxy2;
   float cyy, mxx, mxy2, myy;
-  float mz, o, thr, zmin;
+  float mz, o, thr, pad0;
   float m[9];
   float mu[3];
-  uint32_t rx, ry;      // pixel rectangle x0 | x1 << 16, y0 | y1 << 16
-  uint32_t pad0, pad1;
 };
 
 struct QueryArgs {
@@ -169,8 +170,10 @@ struct QueryArgs {
   const float4* world;
   const short4* rect;
   const int2* granges;          // Gaussian tile lists
-  const uint32_t* gvals;
-  const int32_t* ggid;
+  const uint32_t* gvals;        // Gaussian ids (compact lists) or emission indices
+  const int32_t* ggid;          // emission index -> Gaussian id (64-bit lists only)
+  int key_shift;                // depth key of the lists (query_depth_key)
+  int compact;
   const int2* pranges;          // point lists per tile
   const uint32_t* pvals;
   const int32_t* blk_off;
@@ -213,6 +216,7 @@ __global__ __launch_bounds__(kQueryBlock) void k_query_eval(QueryArgs a) {
       zx = (float)zc;
       cur = a.out[p];
     }
+    const uint32_t qx = query_depth_key(zx, a.key_shift);
     float T = 1.f;
     bool pruned = false;
     const int2 gr = a.granges[t];
@@ -220,7 +224,7 @@ __global__ __launch_bounds__(kQueryBlock) void k_query_eval(QueryArgs a) {
       if (__syncthreads_count(!done) == 0) break;
       const int gi = gs + (int)threadIdx.x;
       if (gi < gr.y) {
-        const int32_t g = a.ggid[a.gvals[gi]];
+        const int32_t g = a.compact ? (int32_t)a.gvals[gi] : a.ggid[a.gvals[gi]];
         const int64_t vg = cam_base + g;
         const float4 r0 = a.geom[4 * vg], r1 = a.geom[4 * vg + 1], r2 = a.geom[4 * vg + 2], r3 = a.geom[4 * vg + 3];
         const float4 w0 = a.world[4 * g], w1 = a.world[4 * g + 1], w2 = a.world[4 * g + 2];
@@ -228,14 +232,14 @@ __global__ __launch_bounds__(kQueryBlock) void k_query_eval(QueryArgs a) {
         e.ui = __float_as_int(r0.x); e.uf = r0.y; e.vi = __float_as_int(r0.z); e.vf = r0.w;
         e.gx = r1.x; e.gy = r1.y; e.cxx = r1.z; e.cxy2 = r1.w;
         e.cyy = r2.x; e.mxx = r2.y; e.mxy2 = r2.z; e.myy = r2.w;
-        e.mz = r3.x; e.o = r3.y; e.thr = r3.z; e.zmin = a.zmin[vg];
+        e.mz = r3.x; e.o = r3.y; e.thr = r3.z; e.pad0 = 0.f; e.zmin = a.zmin[vg];
         e.m[0] = w0.x; e.m[1] = w0.y; e.m[2] = w0.z; e.m[3] = w0.w;
         e.m[4] = w1.x; e.m[5] = w1.y; e.m[6] = w1.z; e.m[7] = w1.w;
         e.m[8] = w2.x; e.mu[0] = w2.y; e.mu[1] = w2.z; e.mu[2] = w2.w;
         const short4 rc = a.rect[vg];
         e.rx = (uint32_t)(uint16_t)rc.x | ((uint32_t)(uint16_t)rc.z << 16);
         e.ry = (uint32_t)(uint16_t)rc.y | ((uint32_t)(uint16_t)rc.w << 16);
-        e.pad0 = 0u; e.pad1 = 0u;
+        e.qz = query_depth_key(e.zmin, a.key_shift);
         stage[threadIdx.x] = e;
       }
       __syncthreads();
@@ -246,10 +250,13 @@ __global__ __launch_bounds__(kQueryBlock) void k_query_eval(QueryArgs a) {
       for (int j = 0; j < nb; ++j) {
         if (!__any(!done)) break;
         const StageQ& e = stage[j];
-        const float zmin = e.zmin;
-        const uint32_t rx = e.rx, ry = e.ry;
-        done = done || (zmin > zx);                    // lists are sorted by z_min
-        const bool in = !done && uxi >= (int)(rx & 0xFFFFu) && uxi <= (int)(rx >> 16) &&
+        const uint4 head = *reinterpret_cast<const uint4*>(&stage[j]);
+        const float zmin = __uint_as_float(head.x);
+        const uint32_t qz = head.y, rx = head.z, ry = head.w;
+        // lists are sorted by a monotone key of z_min: past the point's key every later entry
+        // lies beyond the point; inside its bucket the exact z_min decides
+        done = done || (qz > qx);
+        const bool in = !done && zmin <= zx && uxi >= (int)(rx & 0xFFFFu) && uxi <= (int)(rx >> 16) &&
                         vyi >= (int)(ry & 0xFFFFu) && vyi <= (int)(ry >> 16);
         if (!__any(in)) continue;
         const float dx = (float)(uxi - e.ui) + (uxf - e.uf);
@@ -332,8 +339,9 @@ int sof_opacity_query(const sof_gaussians* g, const sof_camera* h_cams, const so
 
   // 1-2: Gaussians -> per (view, tile) lists sorted by z_min
   if ((e = launch_project(g, d_cams, n_cams, near_plane, proj, s, true)) != hipSuccess) return SOF_E_HIP;
-  int gpar = 0;
-  if ((e = launch_bin_sort(n, d_cams, n_cams, n_tiles, tile, opts->capacity, 1, proj, bins, s, &gpar)) != hipSuccess)
+  int gpar = 0, gdbits = 0;
+  if ((e = launch_query_bin_sort(n, d_cams, n_cams, n_tiles, tile, opts->capacity, proj, bins, s, &gpar, &gdbits)) !=
+      hipSuccess)
     return SOF_E_HIP;
   const ProjLayout P = ProjLayout::make(vn, true, n);
   const BinsLayout B = BinsLayout::make(vn, n_cams, opts->capacity, n_tiles);
@@ -399,6 +407,8 @@ int sof_opacity_query(const sof_gaussians* g, const sof_camera* h_cams, const so
   qa.world = (const float4*)(pbase + P.world);
   qa.granges = (const int2*)(bbase + B.ranges);
   qa.gvals = (const uint32_t*)(bbase + (gpar ? B.vals1 : B.vals0));
+  qa.key_shift = query_key_shift(gdbits);
+  qa.compact = gdbits > 0 ? 1 : 0;
   qa.ggid = (const int32_t*)(bbase + B.gid);
   qa.pranges = pranges;
   qa.pvals = pv;

@@ -134,4 +134,20 @@ inline __host__ __device__ uint32_t float_order_bits(float f) {
   return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
 }
 
+// Depth key of the query's tile lists.  shift < 0: the exact order of the float.  Otherwise
+// a monotone integer quantisation of it: offset of the float's order bits above those of
+// 2^-10, clamped to 28 bits (32 octaves), shifted right by `shift`.  Monotone (z1 <= z2 gives
+// key(z1) <= key(z2)) and computed with integer operations only, so every kernel that
+// evaluates it on the same float gets the same key.
+constexpr float kQueryKeyBase = 0.0009765625f;
+inline __host__ __device__ int query_key_shift(int dbits) { return dbits <= 0 ? -1 : (dbits >= 28 ? 0 : 28 - dbits); }
+inline __host__ __device__ uint32_t query_depth_key(float z, int shift) {
+  const uint32_t b = float_order_bits(z);
+  if (shift < 0) return b;
+  const uint32_t base = float_order_bits(kQueryKeyBase);
+  const uint32_t lim = (1u << 28) - 1u;
+  const uint32_t d = b > base ? b - base : 0u;
+  return (d < lim ? d : lim) >> shift;
+}
+
 }  // namespace sof

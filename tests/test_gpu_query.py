@@ -102,3 +102,26 @@ def test_query_capacity_growth_and_empty():
     far = np.full((10, 3), 100.0, np.float32)             # seen by no camera -> 1
     got, _ = _run(scene, cams, far)
     assert np.all(got == 1.0)
+
+
+def test_query_wide_tile_ids_use_exact_lists():
+    """More than 2^20 tiles (36 views of 1920x1080 at tile 8): the tile lists fall back to
+    64-bit keys with exact z_min order.  Matches the oracle, and the compact lists of three
+    12-view calls to 1e-6 (the two list orders multiply the same factors in another order)."""
+    scene = scenes.small_scene(300, seed=12)
+    cams = [scenes.circle_camera(2 * np.pi * k / 36, 1920, 1080, radius=3.0, height_y=0.4 * (-1) ** k)
+            for k in range(36)]
+    tiles = sum(((c["width"] + 7) // 8) * ((c["height"] + 7) // 8) for c in cams)
+    assert tiles > 2 ** 20
+    pts = scenes.random_points(300, seed=13, low=-1.0, high=1.0)
+    print(f"[case] query {tiles} tiles, 36 views 1920x1080, {len(pts)} points", flush=True)
+    got, _ = _run(scene, cams, pts, tile=8)
+    ref = _oracle(scene, cams, pts)
+    err = np.abs(got - ref)
+    print(f"max err {err.max():.2e}")
+    assert err.max() <= TOL
+    per = np.ones(len(pts), np.float32)
+    for k in range(0, 36, 12):                       # 12 views per call: compact lists
+        o, _ = _run(scene, cams[k:k + 12], pts, tile=8)
+        per = np.minimum(per, o)
+    assert np.abs(got - per).max() <= 1e-6
