@@ -45,8 +45,8 @@ KERNEL_SOURCES = {
     "k_render_bwd": ("render_bwd.hip", "render_common.h", "sof_internal.h", "launch.h"),
 }
 COUNTERS = {                        # kernel -> sources hash, counter KiB per dispatch
-    "k_render_bwd": {"src": "cdbfbee793385fca", "fetch_kib": 586162.7, "write_kib": 258460.2},
-    "k_render_fwd": {"src": "703224e307dc2bbe", "fetch_kib": 332043.8, "write_kib": 124426.9},
+    "k_render_bwd": {"src": "f4f6c558311f2896", "fetch_kib": 663503.0, "write_kib": 211863.2},
+    "k_render_fwd": {"src": "be6461e92c092203", "fetch_kib": 332055.3, "write_kib": 124423.2},
 }
 COUNTER_SCALE = {"fetch": 0.50002, "write": 1.0}    # counter KiB per KiB moved by the 1 GiB copy
 
