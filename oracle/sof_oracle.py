@@ -20,6 +20,8 @@ paper's definitions:
   cites StopThePop for it and does not restate it; the two-level reading used here is
   documented at `hierarchical_order`)
 * opacity-sorted early stop for queries (z_min)     -- Sec. 3.4 "Early Stopping", Eq. (15)
+* level-set classification and binary search         -- Sec. 3.4 (8 binary-search steps
+  towards the 0.5 level set; only O > 0.5 or not matters there)
 
 Readings of passages the paper leaves open (all listed in the design notes):
   R1  A, B, C are written with Sigma^{-1} directly (A = d^T S^-1 d, B = 2 d^T S^-1 (o-mu),
@@ -42,6 +44,10 @@ Readings of passages the paper leaves open (all listed in the design notes):
   R9  colour: real spherical harmonics (Condon-Shortley phase), + 0.5, clamped at 0,
       evaluated at the unit direction from the camera centre to the mean.
   R10 an unobserved query point (no valid view) has opacity 1 (identity of min on [0,1]).
+  R16 binary search: a point is inside when O(x) > 0.5; an edge joins an inside endpoint a
+      and an outside endpoint b; each step evaluates the midpoint and replaces the endpoint
+      of the same class; the result after the last step is the midpoint of the final
+      bracket (the paper gives the step count, 8, not the final pick).
 """
 
 from __future__ import annotations
@@ -604,3 +610,30 @@ def fd_gradient(scene: Scene, cams, window, pixel_lists, weights, depth_mode="ex
             ok[i] = sp == sm
         out[name] = (g.reshape(base.shape), ok.reshape(base.shape))
     return out
+
+
+# ----------------------------------------------------------------------------------------
+# Level set of the opacity field: classification and binary search (Sec. 3.4)
+# ----------------------------------------------------------------------------------------
+
+def inside(scene: Scene, cams, points, views=None):
+    """O(x) > 0.5 for every point (the only thing the binary search needs)."""
+    return opacity_field(scene, cams, points, views) > 0.5
+
+
+def bisect_level_set(scene: Scene, cams, a, b, steps=8):
+    """Binary search on edges (a[i] inside, b[i] outside) for the 0.5 level set (R16).
+
+    Returns the final midpoints and the per-step decisions [steps, n] (True: the midpoint
+    was inside, so it replaced a)."""
+    views = [view(scene, c) for c in cams]
+    a = np.array(a, np.float64)
+    b = np.array(b, np.float64)
+    decisions = []
+    for _ in range(steps):
+        mid = 0.5 * (a + b)
+        ins = inside(scene, cams, mid, views)
+        a = np.where(ins[:, None], mid, a)
+        b = np.where(ins[:, None], b, mid)
+        decisions.append(ins)
+    return 0.5 * (a + b), np.array(decisions).reshape(steps, len(a))

@@ -443,3 +443,55 @@ def test_fd_recovers_analytic_derivatives():
     np.testing.assert_allclose(g["means"][0][0], [0, 0, 1.0], atol=1e-6)
     # d/do of D - s sqrt(2 ln 2o) = -s / (o sqrt(2 ln 2o))
     assert g["opac"][0][0] == pytest.approx(-s / (o * math.sqrt(2 * math.log(2 * o))), rel=1e-6)
+
+
+# --------------------------------------------------------------------------- level set (Sec. 3.4)
+
+def test_bisection_on_the_axis_of_one_gaussian():
+    """One isotropic Gaussian on the optical axis: in front of the peak O(x) = o exp(-(D-t)^2 /
+    (2 s^2)), beyond it O = o, so the 0.5 level set is t0 = D - s sqrt(2 ln 2o) and a point
+    is inside iff t > t0.  Eight halvings of [3.0, 4.5] against that closed form give the
+    same decisions and the same final midpoint."""
+    D, s, o = 4.0, 0.3, 0.8
+    sc = one_gaussian((0, 0, D), s, o)
+    cam = O.Camera(np.eye(3), np.zeros(3), 100.0, 100.0, 2.0, 2.0, 4, 4)
+    t0 = D - s * math.sqrt(2.0 * math.log(2.0 * o))
+    assert t0 == pytest.approx(3.709138, abs=1e-6)
+    a, b = np.array([[0.0, 0.0, 4.5]]), np.array([[0.0, 0.0, 3.0]])
+    got, dec = O.bisect_level_set(sc, [cam], a, b, steps=8)
+    lo, hi, expect = 3.0, 4.5, []
+    for _ in range(8):
+        m = 0.5 * (lo + hi)
+        expect.append(m > t0)
+        lo, hi = (lo, m) if m > t0 else (m, hi)
+    assert dec[:, 0].tolist() == expect
+    assert got[0, 2] == 0.5 * (lo + hi)
+    assert abs(got[0, 2] - t0) <= 1.5 / 2 ** 9
+    assert got[0, 0] == 0.0 and got[0, 1] == 0.0
+
+
+def test_bisection_keeps_a_bracket_in_a_scene():
+    """Small scene, three views: every final bracket still has an inside and an outside end,
+    has length |b - a| / 2^8 and contains the returned point."""
+    scene = scenes.small_scene(120, seed=3)
+    sc = O.Scene.from_arrays(**scene)
+    cams = [O.Camera.from_arrays(**scenes.circle_camera(2 * math.pi * k / 3, 64, 48, radius=3.0)) for k in range(3)]
+    rng = np.random.default_rng(0)
+    cand_a = sc.means[rng.choice(sc.n, 40, replace=False)]
+    cand_b = cand_a + rng.normal(0, 1, cand_a.shape) * 0.5
+    ins_a = O.inside(sc, cams, cand_a)
+    ins_b = O.inside(sc, cams, cand_b)
+    keep = ins_a != ins_b
+    assert keep.sum() >= 5
+    a = np.where(ins_a[keep, None], cand_a[keep], cand_b[keep])
+    b = np.where(ins_a[keep, None], cand_b[keep], cand_a[keep])
+    got, dec = O.bisect_level_set(sc, cams, a, b, steps=8)
+    # rebuild the final brackets from the decisions
+    lo, hi = a.copy(), b.copy()
+    for d in dec:
+        m = 0.5 * (lo + hi)
+        lo = np.where(d[:, None], m, lo)
+        hi = np.where(d[:, None], hi, m)
+    assert np.all(O.inside(sc, cams, lo)) and not np.any(O.inside(sc, cams, hi))
+    assert np.allclose(np.linalg.norm(hi - lo, axis=1), np.linalg.norm(b - a, axis=1) / 256, rtol=1e-12)
+    assert np.allclose(got, 0.5 * (lo + hi), rtol=0, atol=0)
