@@ -67,8 +67,11 @@ enum {
   SOF_DEPTH_GRAD_FULL = 1u << 1, /* render_bwd: differentiate the exact-depth correction
                                     (App. A.3) too; default treats it as a constant, as the
                                     paper does, so d depth = d t*_k                           */
-  SOF_QUERY_KEYS = 1u << 2       /* set internally by sof_opacity_query: tile lists sorted by
+  SOF_QUERY_KEYS = 1u << 2,      /* set internally by sof_opacity_query: tile lists sorted by
                                     z_min (Eq. (15)) instead of the mean's view depth          */
+  SOF_QUERY_LEVELSET = 1u << 3   /* sof_opacity_query: only O(x) > 0.5 or not is needed
+                                    (Sec. 3.4): stop a view once its O_N exceeds 0.5 and skip
+                                    a point once some view gave O_N <= 0.5                    */
 };
 
 /* Gaussians, Sec. 3.1: n primitives, activated parameters. */
@@ -200,7 +203,9 @@ int sof_query_workspace_size(int64_t n, const sof_camera* h_cams, int32_t n_cams
  * sorted by a monotone key of z_min (32-bit keys quantise it to 1/128 octave when the tile
  * ids fit in 20 bits, 64-bit keys keep it exact otherwise) and the walk stops once the key
  * passes the point's own (Eq. (15); inside the point's bucket the exact z_min decides) or
- * once the partial O_N already reaches the point's running minimum.  All (view, tile, block) work items run in
+ * once the partial O_N already reaches the point's running minimum.  With
+ * SOF_QUERY_LEVELSET in opts->flags the result is exact only up to the classification the
+ * binary search needs: opacity[p] = O(x) when O(x) <= 0.5, otherwise a value in (0.5, O(x)].  All (view, tile, block) work items run in
  * one persistent launch.  Overwrites opacity [n_points].
  */
 int sof_opacity_query(const sof_gaussians* g, const sof_camera* h_cams, const sof_camera* d_cams,
@@ -219,6 +224,18 @@ int sof_opacity_query(const sof_gaussians* g, const sof_camera* h_cams, const so
  * thread-safe.  Always returns SOF_OK.
  */
 int sof_set_timing_events(void* const* events);
+
+/*
+ * sof_bisect_step -- one step of the binary search towards the 0.5 level set of the opacity
+ * field (Sec. 3.4: eight steps on the edges of the tetrahedral grid).  a, b and mid are
+ * device [n_edges, 3] float32 arrays: a[i] an endpoint inside (O > 0.5), b[i] one outside.
+ * With opacity == NULL the call only writes mid = (a + b) / 2.  Otherwise opacity[i] is the
+ * opacity at mid[i] (e.g. from sof_opacity_query with SOF_QUERY_LEVELSET): mid replaces a
+ * when opacity > 0.5 and b otherwise, then mid is set to the new (a + b) / 2.  Arrays are
+ * caller-owned and updated in place; after k steps mid is the centre of a bracket 2^-k the
+ * initial length.  Returns SOF_E_ARG for null arrays (with n_edges > 0) or n_edges < 0.
+ */
+int sof_bisect_step(float* a, float* b, float* mid, const float* opacity, int64_t n_edges, hipStream_t stream);
 
 /* Human-readable text for a sof_status value (static storage). */
 const char* sof_strerror(int code);

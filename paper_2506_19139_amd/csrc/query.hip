@@ -174,6 +174,7 @@ struct QueryArgs {
   const int32_t* ggid;          // emission index -> Gaussian id (64-bit lists only)
   int key_shift;                // depth key of the lists (query_depth_key)
   int compact;
+  int levelset;                 // only O > 0.5 or not is needed
   const int2* pranges;          // point lists per tile
   const uint32_t* pvals;
   const int32_t* blk_off;
@@ -217,8 +218,10 @@ __global__ __launch_bounds__(kQueryBlock) void k_query_eval(QueryArgs a) {
       cur = a.out[p];
     }
     const uint32_t qx = query_depth_key(zx, a.key_shift);
+    // level set: some view already gave O_N <= 1/2, so the minimum stays there
+    bool pruned = a.levelset && active && cur <= 0.5f;
+    done = done || pruned;
     float T = 1.f;
-    bool pruned = false;
     const int2 gr = a.granges[t];
     for (int gs = gr.x; gs < gr.y; gs += kQueryBlock) {
       if (__syncthreads_count(!done) == 0) break;
@@ -280,12 +283,34 @@ __global__ __launch_bounds__(kQueryBlock) void k_query_eval(QueryArgs a) {
         ok = ok && al >= kAlphaMin;
         T = ok ? T * (1.f - al) : T;
         const bool prune = ok && (1.f - T >= cur);
+        const bool half = a.levelset && ok && (1.f - T > 0.5f);   // this view's O_N exceeds 1/2
         pruned = pruned || prune;
-        done = done || prune;
+        done = done || prune || half;
       }
     }
     if (active && !pruned) atomicMin((unsigned int*)(a.out + p), __float_as_uint(1.f - T));
   }
+}
+
+__global__ __launch_bounds__(256) void k_bisect_step(float* a, float* b, float* mid, const float* opacity,
+                                                     int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float ax = a[3 * i], ay = a[3 * i + 1], az = a[3 * i + 2];
+  float bx = b[3 * i], by = b[3 * i + 1], bz = b[3 * i + 2];
+  if (opacity) {
+    const float mx = mid[3 * i], my = mid[3 * i + 1], mz = mid[3 * i + 2];
+    if (opacity[i] > 0.5f) {
+      ax = mx; ay = my; az = mz;
+      a[3 * i] = ax; a[3 * i + 1] = ay; a[3 * i + 2] = az;
+    } else {
+      bx = mx; by = my; bz = mz;
+      b[3 * i] = bx; b[3 * i + 1] = by; b[3 * i + 2] = bz;
+    }
+  }
+  mid[3 * i] = 0.5f * (ax + bx);
+  mid[3 * i + 1] = 0.5f * (ay + by);
+  mid[3 * i + 2] = 0.5f * (az + bz);
 }
 
 }  // namespace sof
@@ -293,6 +318,15 @@ __global__ __launch_bounds__(kQueryBlock) void k_query_eval(QueryArgs a) {
 using namespace sof;
 
 extern "C" {
+
+int sof_bisect_step(float* a, float* b, float* mid, const float* opacity, int64_t n_edges, hipStream_t stream) {
+  if (n_edges < 0) return SOF_E_ARG;
+  if (n_edges == 0) return SOF_OK;
+  if (!a || !b || !mid) return SOF_E_ARG;
+  hipLaunchKernelGGL(k_bisect_step, dim3((unsigned)div_up(n_edges, 256)), dim3(256), 0, stream, a, b, mid, opacity,
+                     n_edges);
+  return hipGetLastError() == hipSuccess ? SOF_OK : SOF_E_HIP;
+}
 
 int sof_query_workspace_size(int64_t n, const sof_camera* h_cams, int32_t n_cams, const sof_options* opts,
                              int64_t n_points, int64_t pv_capacity, size_t* proj_bytes, size_t* bins_bytes,
@@ -409,6 +443,7 @@ int sof_opacity_query(const sof_gaussians* g, const sof_camera* h_cams, const so
   qa.gvals = (const uint32_t*)(bbase + (gpar ? B.vals1 : B.vals0));
   qa.key_shift = query_key_shift(gdbits);
   qa.compact = gdbits > 0 ? 1 : 0;
+  qa.levelset = (opts->flags & SOF_QUERY_LEVELSET) ? 1 : 0;
   qa.ggid = (const int32_t*)(bbase + B.gid);
   qa.pranges = pranges;
   qa.pvals = pv;

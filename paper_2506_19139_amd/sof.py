@@ -21,6 +21,7 @@ SOF_OK, SOF_E_ARG, SOF_E_WORKSPACE, SOF_E_CAPACITY, SOF_E_HIP, SOF_E_UNSUPPORTED
 SOF_DEPTH_MEDIAN = 1 << 0
 SOF_DEPTH_GRAD_FULL = 1 << 1
 SOF_QUERY_KEYS = 1 << 2
+SOF_QUERY_LEVELSET = 1 << 3
 
 WINDOWS = (0, 1, 2, 4, 8, 16, 32)
 AUX_CHANNELS = 6      # T_end, n_emitted, k, T_k, entries tested, candidates
@@ -70,6 +71,7 @@ _SIGS = {
     "sof_opacity_query": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, _P, _P, ctypes.c_int64, ctypes.c_int64,
                                          _P, _P, ctypes.c_size_t, _P, ctypes.c_size_t, _P, ctypes.c_size_t, _P]),
     "sof_set_timing_events": (ctypes.c_int, [_P]),
+    "sof_bisect_step": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int64, _P]),
     "sof_strerror": (ctypes.c_char_p, [ctypes.c_int]),
 }
 
@@ -483,6 +485,47 @@ class OpacityQuery:
             if not grow:
                 break
         return out
+
+
+def bisect_step(a: torch.Tensor, b: torch.Tensor, mid: torch.Tensor, opacity: torch.Tensor = None):
+    """One binary-search step on edges (a inside, b outside; [n, 3] float32, updated in place):
+    with `opacity` (at mid) the midpoint replaces a or b, then mid = (a + b) / 2."""
+    n = int(a.shape[0])
+    assert a.shape == b.shape == mid.shape and a.dtype == b.dtype == mid.dtype == torch.float32
+    assert a.is_contiguous() and b.is_contiguous() and mid.is_contiguous()
+    if opacity is not None:
+        assert opacity.shape == (n,) and opacity.dtype == torch.float32 and opacity.is_contiguous()
+    _check(lib().sof_bisect_step(_ptr(a), _ptr(b), _ptr(mid), _ptr(opacity), n, _stream()), "sof_bisect_step")
+
+
+class LevelSetSearch:
+    """Binary search towards the 0.5 level set of the opacity field over a camera set
+    (Sec. 3.4): the opacity at the midpoints comes from level-set queries (stop a view
+    at O_N > 0.5, skip points some view put at or below 0.5), one launch per step."""
+
+    def __init__(self, cams: Cameras, tile=8, device="cuda"):
+        self.query = OpacityQuery(cams, Options(tile=tile, flags=SOF_QUERY_LEVELSET), device=device)
+
+    def orient(self, g: Gaussians, p: torch.Tensor, q: torch.Tensor):
+        """Edges (p, q) whose ends lie on opposite sides of the level set, as (inside, outside)
+        pairs."""
+        op = self.query(g, p).clone()
+        oq = self.query(g, q)
+        ip, iq = op > 0.5, oq > 0.5
+        keep = ip != iq
+        a = torch.where(ip[keep, None], p[keep], q[keep]).contiguous()
+        b = torch.where(ip[keep, None], q[keep], p[keep]).contiguous()
+        return a, b
+
+    def __call__(self, g: Gaussians, a: torch.Tensor, b: torch.Tensor, steps=8):
+        """Final midpoints after `steps` halvings (a and b are updated in place)."""
+        mid = torch.empty_like(a)
+        bisect_step(a, b, mid)
+        o = torch.empty(a.shape[0], dtype=torch.float32, device=a.device)
+        for _ in range(steps):
+            self.query(g, mid, out=o)
+            bisect_step(a, b, mid, o)
+        return mid
 
 
 def opacity_query(g: Gaussians, cams: Cameras, points: torch.Tensor, opts: Options = None):
