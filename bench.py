@@ -83,6 +83,8 @@ def parse():
     ap.add_argument("--no-per-view", action="store_true",
                     help="skip the comparison against one query launch per view")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-levelset", action="store_true",
+                    help="skip the level-set query and the binary search")
     ap.add_argument("--no-multiview", action="store_true",
                     help="skip the 8-camera graph-captured training step")
     ap.add_argument("--cpu-pixels", type=int, default=160)
@@ -206,6 +208,51 @@ def multiview_step(g, stream, reps=10):
             "mpx_per_s": round(cams.n_pixels / (ms * 1e-3) / 1e6, 1), "instances": int(k_used),
             "tuner_window8_ms": round(tile8[2], 3),
             "tuner_over_tile_and_window": {"tile": full[0], "window": full[1], "ms": round(full[2], 3)}}
+
+
+def levelset_search(qg, pts, qcams, tile, t_exact, stream, steps=8):
+    """The query in level-set mode (only O > 0.5 or not) over the same 27M points, then eight
+    binary-search steps on edges from each Gaussian's centre to one of its 3-sigma box corners
+    that cross the level set (synthetic stand-ins for the edges of a tetrahedral grid)."""
+    import torch
+    from paper_2506_19139_amd import sof
+    search = sof.LevelSetSearch(qcams, tile=tile)
+    o = search.query(qg, pts)
+    search.query.auto_capacity = False
+    times = []
+    for _ in range(2):
+        a_, b_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a_.record(stream)
+        search.query(qg, pts, out=o)
+        b_.record(stream)
+        torch.cuda.synchronize()
+        times.append(a_.elapsed_time(b_))
+    tl = float(np.median(times))
+    n = pts.shape[0] // 9
+    ins = (o > 0.5).view(n, 9)
+    corner = 1 + torch.arange(n, device=pts.device) % 8
+    p9 = pts.view(n, 9, 3)
+    keep = ins[:, 0] != ins[torch.arange(n, device=pts.device), corner]
+    cen, cor = p9[keep, 0], p9[torch.nonzero(keep).squeeze(1), corner[keep]]
+    cin = ins[keep, 0]
+    a = torch.where(cin[:, None], cen, cor).contiguous()
+    b = torch.where(cin[:, None], cor, cen).contiguous()
+    search.query.pv_capacity = 0                         # new point set: size the pair buffers again
+    search.query.auto_capacity = True
+    a1, b1 = a.clone(), b.clone()
+    search(qg, a1, b1, steps=1)                          # sizing pass
+    search.query.auto_capacity = False
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    search(qg, a, b, steps=steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    tb = e0.elapsed_time(e1)
+    return {"query_ms": round(tl, 2), "points_per_s": round(pts.shape[0] / (tl * 1e-3), 1),
+            "speedup_vs_exact": round(t_exact / tl, 2), "inside_fraction": round(float((o > 0.5).float().mean()), 4),
+            "bisection": {"edges": int(a.shape[0]), "steps": steps, "ms": round(tb, 2),
+                          "ms_per_step": round(tb / steps, 2)}}
 
 
 # --------------------------------------------------------------------------- GPU
@@ -367,6 +414,9 @@ def main():
         if not args.no_per_view:
             log("query, one launch per view")
             result["query"]["per_view_launches"] = per_view_query(qg, pts, qcams, args.query_tile, o, tq, stream)
+        if not args.no_levelset:
+            log("level-set query and binary search")
+            result["levelset"] = levelset_search(qg, pts, qcams, args.query_tile, tq, stream)
         del q, qg, pts, o
         torch.cuda.empty_cache()
 

@@ -69,9 +69,13 @@ enum {
                                     paper does, so d depth = d t*_k                           */
   SOF_QUERY_KEYS = 1u << 2,      /* set internally by sof_opacity_query: tile lists sorted by
                                     z_min (Eq. (15)) instead of the mean's view depth          */
-  SOF_QUERY_LEVELSET = 1u << 3   /* sof_opacity_query: only O(x) > 0.5 or not is needed
+  SOF_QUERY_LEVELSET = 1u << 3,  /* sof_opacity_query: only O(x) > 0.5 or not is needed
                                     (Sec. 3.4): stop a view once its O_N exceeds 0.5 and skip
                                     a point once some view gave O_N <= 0.5                    */
+  SOF_QUERY_REUSE = 1u << 4      /* sof_opacity_query: proj and bins still hold the Gaussian
+                                    side (projection, per-tile lists) of the previous call with
+                                    the same Gaussians, cameras, tile and capacity; only the
+                                    points are processed (the binary search's later steps)    */
 };
 
 /* Gaussians, Sec. 3.1: n primitives, activated parameters. */

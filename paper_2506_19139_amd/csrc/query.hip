@@ -175,6 +175,7 @@ struct QueryArgs {
   int key_shift;                // depth key of the lists (query_depth_key)
   int compact;
   int levelset;                 // only O > 0.5 or not is needed
+  int cap;                      // instance capacity of the lists
   const int2* pranges;          // point lists per tile
   const uint32_t* pvals;
   const int32_t* blk_off;
@@ -222,12 +223,15 @@ __global__ __launch_bounds__(kQueryBlock) void k_query_eval(QueryArgs a) {
     bool pruned = a.levelset && active && cur <= 0.5f;
     done = done || pruned;
     float T = 1.f;
-    const int2 gr = a.granges[t];
+    int2 gr = a.granges[t];
+    gr.x = max(0, min(gr.x, a.cap));                   // lists are read in bounds whatever bins holds
+    gr.y = max(gr.x, min(gr.y, a.cap));
     for (int gs = gr.x; gs < gr.y; gs += kQueryBlock) {
       if (__syncthreads_count(!done) == 0) break;
       const int gi = gs + (int)threadIdx.x;
       if (gi < gr.y) {
-        const int32_t g = a.compact ? (int32_t)a.gvals[gi] : a.ggid[a.gvals[gi]];
+        int32_t g = a.compact ? (int32_t)a.gvals[gi] : a.ggid[min(a.gvals[gi], (uint32_t)(a.cap - 1))];
+        g = max(0, min(g, (int32_t)a.n - 1));
         const int64_t vg = cam_base + g;
         const float4 r0 = a.geom[4 * vg], r1 = a.geom[4 * vg + 1], r2 = a.geom[4 * vg + 2], r3 = a.geom[4 * vg + 3];
         const float4 w0 = a.world[4 * g], w1 = a.world[4 * g + 1], w2 = a.world[4 * g + 2];
@@ -371,12 +375,18 @@ int sof_opacity_query(const sof_gaussians* g, const sof_camera* h_cams, const so
   const int th = 256;
   hipError_t e = hipSuccess;
 
-  // 1-2: Gaussians -> per (view, tile) lists sorted by z_min
-  if ((e = launch_project(g, d_cams, n_cams, near_plane, proj, s, true)) != hipSuccess) return SOF_E_HIP;
+  // 1-2: Gaussians -> per (view, tile) lists sorted by z_min (or those of the previous call)
   int gpar = 0, gdbits = 0;
-  if ((e = launch_query_bin_sort(n, d_cams, n_cams, n_tiles, tile, opts->capacity, proj, bins, s, &gpar, &gdbits)) !=
-      hipSuccess)
-    return SOF_E_HIP;
+  if ((opts->flags & SOF_QUERY_REUSE) && n > 0) {
+    gdbits = query_key_bits(n_tiles);
+    const int bits = gdbits ? 32 : 32 + bits_for(n_tiles);
+    gpar = ((bits + 7) / 8) & 1;                       // parity of the radix passes that sorted them
+  } else {
+    if ((e = launch_project(g, d_cams, n_cams, near_plane, proj, s, true)) != hipSuccess) return SOF_E_HIP;
+    if ((e = launch_query_bin_sort(n, d_cams, n_cams, n_tiles, tile, opts->capacity, proj, bins, s, &gpar,
+                                   &gdbits)) != hipSuccess)
+      return SOF_E_HIP;
+  }
   const ProjLayout P = ProjLayout::make(vn, true, n);
   const BinsLayout B = BinsLayout::make(vn, n_cams, opts->capacity, n_tiles);
   char* pbase = (char*)proj;
@@ -444,6 +454,7 @@ int sof_opacity_query(const sof_gaussians* g, const sof_camera* h_cams, const so
   qa.key_shift = query_key_shift(gdbits);
   qa.compact = gdbits > 0 ? 1 : 0;
   qa.levelset = (opts->flags & SOF_QUERY_LEVELSET) ? 1 : 0;
+  qa.cap = (int)opts->capacity;
   qa.ggid = (const int32_t*)(bbase + B.gid);
   qa.pranges = pranges;
   qa.pvals = pv;

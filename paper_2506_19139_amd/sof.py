@@ -22,6 +22,7 @@ SOF_DEPTH_MEDIAN = 1 << 0
 SOF_DEPTH_GRAD_FULL = 1 << 1
 SOF_QUERY_KEYS = 1 << 2
 SOF_QUERY_LEVELSET = 1 << 3
+SOF_QUERY_REUSE = 1 << 4
 
 WINDOWS = (0, 1, 2, 4, 8, 16, 32)
 AUX_CHANNELS = 6      # T_end, n_emitted, k, T_k, entries tested, candidates
@@ -452,24 +453,33 @@ class OpacityQuery:
         self.last = (0, 0)
 
     def _alloc(self, n, n_points):
+        """Size the buffers; True if the Gaussian-side buffers were (re)allocated."""
         p, b, s = query_workspace_size(n, self.cams, self.opts, n_points, self.pv_capacity)
+        grown = False
         if self.proj is None or self.proj.numel() < p:
             self.proj = torch.empty(p, dtype=torch.uint8, device=self.device)
+            grown = True
         if self.bins is None or self.bins.numel() < b:
             self.bins = torch.empty(b, dtype=torch.uint8, device=self.device)
+            grown = True
         if self.sched is None or self.sched.numel() < s:
             self.sched = torch.empty(s, dtype=torch.uint8, device=self.device)
+        return grown
 
-    def __call__(self, g: Gaussians, points: torch.Tensor, out=None):
+    def __call__(self, g: Gaussians, points: torch.Tensor, out=None, reuse_gaussians=False):
+        """O(x) for every point.  reuse_gaussians: the buffers still hold the Gaussian side of
+        the previous call with these same Gaussians (skips their projection and sort)."""
         n_points = int(points.shape[0])
         if self.opts.capacity <= 0:
             self.opts.capacity = max(1024, 2 * g.n * len(self.cams))
         if self.pv_capacity <= 0:
             self.pv_capacity = min(n_points * len(self.cams), 2 ** 31 - 1)
         out = torch.empty(n_points, dtype=torch.float32, device=self.device) if out is None else out
-        for _ in range(3):
-            self._alloc(g.n, n_points)
-            opacity_query_raw(g, self.cams, self.opts, points, self.pv_capacity, out, self.proj, self.bins, self.sched)
+        for attempt in range(3):
+            grown = self._alloc(g.n, n_points)
+            reuse = reuse_gaussians and attempt == 0 and not grown and self.proj is not None
+            opts = Options(**{**self.opts.__dict__, "flags": self.opts.flags | (SOF_QUERY_REUSE if reuse else 0)})
+            opacity_query_raw(g, self.cams, opts, points, self.pv_capacity, out, self.proj, self.bins, self.sched)
             if not self.auto_capacity:
                 break
             k_inst, f_inst = read_status(self.bins)
@@ -522,8 +532,9 @@ class LevelSetSearch:
         mid = torch.empty_like(a)
         bisect_step(a, b, mid)
         o = torch.empty(a.shape[0], dtype=torch.float32, device=a.device)
-        for _ in range(steps):
-            self.query(g, mid, out=o)
+        for step in range(steps):
+            # the Gaussian side (projection, tile lists) is built once per search
+            self.query(g, mid, out=o, reuse_gaussians=step > 0)
             bisect_step(a, b, mid, o)
         return mid
 

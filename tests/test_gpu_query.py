@@ -125,3 +125,19 @@ def test_query_wide_tile_ids_use_exact_lists():
         o, _ = _run(scene, cams[k:k + 12], pts, tile=8)
         per = np.minimum(per, o)
     assert np.abs(got - per).max() <= 1e-6
+
+
+def test_reuse_of_the_gaussian_side_matches_a_fresh_query():
+    """SOF_QUERY_REUSE: a second point set against the projection and tile lists left by the
+    previous call gives exactly what a fresh call gives."""
+    scene = scenes.small_scene(300, seed=14)
+    cams = _ring(4)
+    g = sof.Gaussians.from_numpy(scene)
+    C = sof.Cameras(cams)
+    q = sof.OpacityQuery(C, sof.Options(tile=8))
+    p1 = torch.from_numpy(scenes.random_points(400, seed=15, low=-1.0, high=1.0)).cuda()
+    p2 = torch.from_numpy(scenes.random_points(700, seed=16, low=-1.0, high=1.0)).cuda()
+    q(g, p1)
+    reused = q(g, p2, reuse_gaussians=True).cpu().numpy()
+    fresh = sof.OpacityQuery(C, sof.Options(tile=8))(g, p2).cpu().numpy()
+    assert np.array_equal(reused, fresh)
