@@ -22,6 +22,8 @@ paper's definitions:
 * opacity-sorted early stop for queries (z_min)     -- Sec. 3.4 "Early Stopping", Eq. (15)
 * level-set classification and binary search         -- Sec. 3.4 (8 binary-search steps
   towards the 0.5 level set; only O > 0.5 or not matters there)
+* opacity field at the rendered depth (L_opa)         -- Sec. 3.3 "Direct Opacity Field
+  Supervision"
 
 Readings of passages the paper leaves open (all listed in the design notes):
   R1  A, B, C are written with Sigma^{-1} directly (A = d^T S^-1 d, B = 2 d^T S^-1 (o-mu),
@@ -48,6 +50,10 @@ Readings of passages the paper leaves open (all listed in the design notes):
       and an outside endpoint b; each step evaluates the midpoint and replaces the endpoint
       of the same class; the result after the last step is the midpoint of the final
       bracket (the paper gives the step count, 8, not the final pick).
+  R17 opacity at the rendered depth: x = o + t_r d with t_r the exact depth of the pixel;
+      O_N(x) over the Gaussians the pixel blends (the paper's first pass accumulates over
+      them), each with alpha at t_eval = min(t*_j, t_r) as in Eq. (12); undefined without a
+      crossing.  Gradients treat t_r as a constant (as the exact-depth correction).
 """
 
 from __future__ import annotations
@@ -569,29 +575,59 @@ def _scene_with(scene: Scene, name, flat_index, value):
     return Scene(arrs["means"], arrs["scales"], arrs["quats"], arrs["opac"], arrs["sh"], scene.sh_degree)
 
 
-def linear_loss(scene: Scene, cams, window, pixel_lists, weights, depth_mode="exact", bg=(0, 0, 0)):
+def opacity_at_depth(scene: Scene, v: CameraView, px, py, res: PixelResult, t_r=None):
+    """O_N(o + t_r d) over the Gaussians blended at this pixel (R17), or None without a
+    crossing.  t_r defaults to the pixel's exact depth.  Also returns the ids that count
+    (alpha at t_eval >= 1/255 and evaluated point beyond the near plane)."""
+    if res.k < 0:
+        return None, []
+    cam = v.cam
+    o = cam.center
+    d, dc = cam.pixel_ray(px, py)
+    t_r = res.depth if t_r is None else t_r
+    ids = np.asarray(res.order, dtype=np.int64)
+    A, B, C = ray_abc(v.prec[ids], scene.means[ids], o, d)
+    tstar = -B / (2.0 * A)
+    te = np.minimum(tstar, t_r)
+    q = np.maximum(0.0, A * te * te + B * te + C)
+    alpha = np.minimum(ALPHA_MAX, scene.opac[ids] * np.exp(-0.5 * q))
+    zc = te / np.linalg.norm(dc)                              # view z of the evaluated point
+    keep = (alpha >= ALPHA_MIN) & (zc > NEAR)
+    return 1.0 - float(np.prod(1.0 - alpha[keep])), [int(i) for i in ids[keep]]
+
+
+def linear_loss(scene: Scene, cams, window, pixel_lists, weights, depth_mode="exact", bg=(0, 0, 0),
+                opa_weights=None, opa_depths=None):
     """L = sum over cameras and listed pixels of <weights, (rgb, acc, depth, normal)>.
 
     weights[c] is [len(pixel_lists[c]), 8] = (rgb 3, acc, depth, normal 3).  depth_mode
     'exact' uses the 0.5-level-set depth; 'median' uses t*_k (what a detached exact-depth
-    correction differentiates to).  Returns (loss, signature); the signature (emitted ids
-    and crossing index per pixel) tells whether two evaluations lie in the same smooth
-    piece of the function."""
+    correction differentiates to).  opa_weights[c][i] adds that multiple of the opacity at
+    the rendered depth (R17; pixels without a crossing add nothing), evaluated at the fixed
+    ray distance opa_depths[c][i] when given (a detached depth).  Returns (loss, signature);
+    the signature (emitted ids, crossing index and the ids that count in the opacity per
+    pixel) tells whether two evaluations lie in the same smooth piece of the function."""
     loss = 0.0
     sig = []
-    for cam, pix, wts in zip(cams, pixel_lists, weights):
+    for c, (cam, pix, wts) in enumerate(zip(cams, pixel_lists, weights)):
         v = view(scene, cam)
-        for (px, py), w in zip(pix, wts):
+        for i, ((px, py), w) in enumerate(zip(pix, wts)):
             r = render_pixel(scene, v, px, py, window, bg)
             dep = r.depth if depth_mode == "exact" else r.median_depth
             vec = np.concatenate([r.rgb, [r.acc, dep], r.normal])
             loss += float(np.dot(vec, w))
-            sig.append((tuple(r.order), r.k))
+            used = []
+            if opa_weights is not None:
+                t_r = None if opa_depths is None else opa_depths[c][i]
+                on, used = opacity_at_depth(scene, v, px, py, r, t_r)
+                if on is not None:
+                    loss += opa_weights[c][i] * on
+            sig.append((tuple(r.order), r.k, tuple(used)))
     return loss, sig
 
 
 def fd_gradient(scene: Scene, cams, window, pixel_lists, weights, depth_mode="exact",
-                names=PARAM_NAMES, h_rel=1e-6, bg=(0, 0, 0)):
+                names=PARAM_NAMES, h_rel=1e-6, bg=(0, 0, 0), opa_weights=None, opa_depths=None):
     """Central differences of `linear_loss` for every element of the named parameters.
 
     Returns {name: (grad, smooth)}; smooth[i] is False where the two evaluations fall in
@@ -604,8 +640,10 @@ def fd_gradient(scene: Scene, cams, window, pixel_lists, weights, depth_mode="ex
         ok = np.ones(flat.shape, bool)
         for i in range(flat.size):
             h = h_rel * max(1.0, abs(flat[i]))
-            lp, sp = linear_loss(_scene_with(scene, name, i, flat[i] + h), cams, window, pixel_lists, weights, depth_mode, bg)
-            lm, sm = linear_loss(_scene_with(scene, name, i, flat[i] - h), cams, window, pixel_lists, weights, depth_mode, bg)
+            lp, sp = linear_loss(_scene_with(scene, name, i, flat[i] + h), cams, window, pixel_lists, weights, depth_mode,
+                                 bg, opa_weights, opa_depths)
+            lm, sm = linear_loss(_scene_with(scene, name, i, flat[i] - h), cams, window, pixel_lists, weights, depth_mode,
+                                 bg, opa_weights, opa_depths)
             g[i] = (lp - lm) / (2.0 * h)
             ok[i] = sp == sm
         out[name] = (g.reshape(base.shape), ok.reshape(base.shape))

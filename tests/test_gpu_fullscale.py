@@ -130,7 +130,7 @@ def _directional_fd(scene, cams, pixels_per_cam, weights, cam_ids, grads, window
                 lo, sig = O.linear_loss(sc, [oc], window, [pix], [wts], depth_mode="median")
                 # the per-Gaussian normal (shortest axis, flipped to face the camera) is piecewise
                 # constant in the parameters: its jumps are discontinuities the order misses
-                used = sorted({int(i) for order, _ in sig for i in order})
+                used = sorted({int(i) for order, *_ in sig for i in order})
                 total += lo
                 sigs.append((sig, O.gaussian_normals(O.Scene(arr["means"][used], arr["scales"][used],
                                                              arr["quats"][used], arr["opac"][used].reshape(-1),

@@ -495,3 +495,57 @@ def test_bisection_keeps_a_bracket_in_a_scene():
     assert np.all(O.inside(sc, cams, lo)) and not np.any(O.inside(sc, cams, hi))
     assert np.allclose(np.linalg.norm(hi - lo, axis=1), np.linalg.norm(b - a, axis=1) / 256, rtol=1e-12)
     assert np.allclose(got, 0.5 * (lo + hi), rtol=0, atol=0)
+
+
+# --------------------------------------------------------------------------- opacity at the rendered depth (Sec. 3.3)
+
+@pytest.mark.parametrize("theta", [0.0, 0.02, -0.04])
+def test_opacity_at_depth_single_gaussian_is_one_half(theta):
+    """One Gaussian: T_k = 1 and the exact depth solves o G(t_r) = 1/2, so O_N there is 1/2."""
+    sc = one_gaussian((0, 0, 4.0), 0.3, 0.8)
+    cam = axis_camera(theta)
+    v = O.view(sc, cam)
+    r = O.render_pixel(sc, v, 0, 0, 8)
+    on, used = O.opacity_at_depth(sc, v, 0, 0, r)
+    assert used == [0]
+    assert on == pytest.approx(0.5, abs=1e-12)
+
+
+def test_opacity_at_depth_counts_a_gaussian_behind_the_depth():
+    """Two Gaussians on the axis; the crossing is on the first (T 1 -> 0.2), so t_r is its
+    single-Gaussian depth, and the second (peak beyond t_r) counts with its value at t_r:
+    O_N = 1 - (1 - 1/2)(1 - o2 exp(-(D2 - t_r)^2 / (2 s2^2)))."""
+    D1, s1, o1, D2, s2, o2 = 4.0, 0.3, 0.8, 4.3, 0.5, 0.6
+    sc = O.Scene(np.array([[0, 0, D1], [0, 0, D2]], np.float64), np.array([[s1] * 3, [s2] * 3], np.float64),
+                 np.array([[1, 0, 0, 0]] * 2, np.float64), np.array([o1, o2], np.float64), np.zeros((2, 1, 3)), 0)
+    cam = axis_camera(0.0)
+    v = O.view(sc, cam)
+    r = O.render_pixel(sc, v, 0, 0, 8)
+    assert r.k == 0 and r.order == [0, 1]
+    t_r = D1 - s1 * math.sqrt(2.0 * math.log(2.0 * o1))
+    assert r.depth == pytest.approx(t_r, abs=1e-12)
+    a2 = o2 * math.exp(-(D2 - t_r) ** 2 / (2 * s2 * s2))
+    on, used = O.opacity_at_depth(sc, v, 0, 0, r)
+    assert used == [0, 1]
+    assert on == pytest.approx(1.0 - 0.5 * (1.0 - a2), abs=1e-12)
+
+
+def test_opacity_at_depth_equals_the_query_formula_without_termination():
+    """Where a pixel blends every candidate, O_N at its depth over the blended Gaussians is the
+    opacity field of Eq. (12) at that point over all Gaussians (independent code path)."""
+    scene = scenes.small_scene(80, seed=9)
+    sc = O.Scene.from_arrays(**scene)
+    oc = O.Camera.from_arrays(**scenes.circle_camera(0.3, 40, 30, radius=3.0))
+    v = O.view(sc, oc)
+    checked = 0
+    for py in range(30):
+        for px in range(40):
+            r = O.render_pixel(sc, v, px, py, 8)
+            if r.k < 0 or r.n_emitted < len(O.pixel_candidates(sc, v, px, py).idx):
+                continue
+            d, _ = oc.pixel_ray(px, py)
+            x = oc.center + r.depth * d
+            on, _ = O.opacity_at_depth(sc, v, px, py, r)
+            assert on == pytest.approx(O.opacity_field_view(sc, v, x), abs=1e-12)
+            checked += 1
+    assert checked >= 20
