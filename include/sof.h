@@ -14,6 +14,7 @@
  *                      (Eq. (2)/(9)) with a bounded window, front-to-back alpha blending
  *                      (Eq. (1)) of colour, normal and opacity, and the exact 0.5-level-set
  *                      depth (Sec. 3.2 "Exact Depth", App. A.3).
+ *   sof_render_opacity opacity field at each pixel's rendered depth (Sec. 3.3, the L_opa term).
  *   sof_render_bwd     adjoint of render + project: replays each pixel's order front to back,
  *                      recomputing transmittance, and writes gradients for mu, s, q, o, f.
  *   sof_opacity_query  opacity field O(x) = min over views of O_N(x) (Eq. (12)-(13)) at
@@ -172,19 +173,38 @@ int sof_render_fwd(int64_t n, const sof_camera* h_cams, const sof_camera* d_cams
                    hipStream_t stream);
 
 /*
- * sof_render_bwd -- adjoint of sof_render_fwd and sof_project.
+ * sof_render_opacity -- Sec. 3.3 (direct opacity-field supervision).
+ * A second pass after sof_render_fwd (same n, cameras, options, proj and bins; its depth
+ * and aux outputs as inputs): for each pixel with a 0.5 crossing, opacity = O_N(x) at
+ * x = o + t_r d, t_r the depth the forward wrote, over the Gaussians the pixel blended, each
+ * with alpha = min(0.99, o_i G_i(min(t*_i, t_r))) and counted when alpha >= 1/255 and the
+ * evaluated point lies beyond the near plane (Eq. (12)); 0 where there is no crossing.
+ * The pass replays the forward's per-pixel order up to its blend count.  Overwrites
+ * opacity [sum of W H].  The L_opa loss |O_N - 0.5|^2 is the caller's to form.
+ */
+int sof_render_opacity(int64_t n, const sof_camera* h_cams, const sof_camera* d_cams, int32_t n_cams,
+                       const sof_options* opts, const void* proj, size_t proj_bytes, const void* bins,
+                       size_t bins_bytes, const float* depth, const float* aux, float* opacity,
+                       hipStream_t stream);
+
+/*
+ * sof_render_bwd -- adjoint of sof_render_fwd, sof_render_opacity and sof_project.
  * Inputs: the same g, cameras, options, proj and bins as the forward call, its rgb,
  * normal and aux outputs, and upstream gradients d_rgb, d_acc, d_depth, d_normal (NULL =
- * zero).  Each pixel's forward order is replayed front to back; suffix sums come from the
- * stored totals.  Writes (overwrites) d_means [n,3], d_scales [n,3], d_quats [n,4],
- * d_opacities [n], d_sh [n,K,3].  `grads` is scratch.  Deterministic: per-instance partials
- * are reduced in a fixed order.
+ * zero).  d_opacity (NULL = zero) is the upstream gradient of sof_render_opacity's output;
+ * with it, depth and opacity must be the forward's depth and that output.  The depth t_r
+ * at which the opacity is evaluated is held constant (like the exact-depth correction).
+ * Each pixel's forward order is replayed front to back; suffix sums come from the stored
+ * totals.  Writes (overwrites) d_means [n,3], d_scales [n,3], d_quats [n,4], d_opacities
+ * [n], d_sh [n,K,3].  `grads` is scratch.  Deterministic: per-instance partials are reduced
+ * in a fixed order.
  */
 int sof_render_bwd(const sof_gaussians* g, const sof_camera* h_cams, const sof_camera* d_cams,
                    int32_t n_cams, const sof_options* opts, const void* proj, size_t proj_bytes,
                    const void* bins, size_t bins_bytes, const float* rgb, const float* normal,
                    const float* aux, const float* d_rgb, const float* d_acc, const float* d_depth,
-                   const float* d_normal, void* grads, size_t grad_bytes, float* d_means,
+                   const float* d_normal, const float* depth, const float* opacity,
+                   const float* d_opacity, void* grads, size_t grad_bytes, float* d_means,
                    float* d_scales, float* d_quats, float* d_opacities, float* d_sh,
                    hipStream_t stream);
 

@@ -181,11 +181,28 @@ int sof_render_fwd(int64_t n, const sof_camera* h_cams, const sof_camera* d_cams
   return hip_status(e);
 }
 
+int sof_render_opacity(int64_t n, const sof_camera* h_cams, const sof_camera* d_cams, int32_t n_cams,
+                       const sof_options* opts, const void* proj, size_t proj_bytes, const void* bins,
+                       size_t bins_bytes, const float* depth, const float* aux, float* opacity, hipStream_t stream) {
+  RenderOpaArgs a;
+  int64_t n_tiles = 0;
+  int st = fill_fwd_args(n, h_cams, d_cams, n_cams, opts, proj, proj_bytes, bins, bins_bytes, &a.f, &n_tiles);
+  if (st) return st;
+  if (!depth || !aux || !opacity) return SOF_E_ARG;
+  a.f.depth = (float*)depth;
+  a.f.aux = (float*)aux;
+  a.opa = opacity;
+  if (trace_enabled())
+    fprintf(stderr, "[sof] render_opacity tiles=%lld tile=%d window=%d\n", (long long)n_tiles, opts->tile, opts->window);
+  return hip_status(launch_render_opa(a, opts->tile, opts->window, n_tiles, stream));
+}
+
 int sof_render_bwd(const sof_gaussians* g, const sof_camera* h_cams, const sof_camera* d_cams, int32_t n_cams,
                    const sof_options* opts, const void* proj, size_t proj_bytes, const void* bins, size_t bins_bytes,
                    const float* rgb, const float* normal, const float* aux, const float* d_rgb, const float* d_acc,
-                   const float* d_depth, const float* d_normal, void* grads, size_t grad_bytes, float* d_means,
-                   float* d_scales, float* d_quats, float* d_opacities, float* d_sh, hipStream_t stream) {
+                   const float* d_depth, const float* d_normal, const float* depth, const float* opacity,
+                   const float* d_opacity, void* grads, size_t grad_bytes, float* d_means, float* d_scales,
+                   float* d_quats, float* d_opacities, float* d_sh, hipStream_t stream) {
   int st = check_gauss(g, true);
   if (st) return st;
   RenderBwdArgs b;
@@ -206,6 +223,10 @@ int sof_render_bwd(const sof_gaussians* g, const sof_camera* h_cams, const sof_c
   b.d_rgb = d_rgb; b.d_acc = d_acc; b.d_depth = d_depth; b.d_normal = d_normal;
   b.grads = (float*)grads;
   b.f.aux = (float*)aux;
+  if (d_opacity && (!depth || !opacity)) return SOF_E_ARG;
+  b.out_depth = d_opacity ? depth : nullptr;
+  b.opa = d_opacity ? opacity : nullptr;
+  b.d_opa = d_opacity;
   if (trace_enabled())
     fprintf(stderr, "[sof] render_bwd tiles=%lld tile=%d window=%d\n", (long long)n_tiles, opts->tile, opts->window);
   timing_mark(kTimeRenderBwd, 0, stream);

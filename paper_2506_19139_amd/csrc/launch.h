@@ -59,10 +59,20 @@ struct RenderBwdArgs {
   const float* d_depth;
   const float* d_normal;
   float* grads;             // [cap, 16] per emission index
+  // opacity at the rendered depth (all null when it has no upstream gradient)
+  const float* out_depth;
+  const float* opa;
+  const float* d_opa;
+};
+
+struct RenderOpaArgs {
+  RenderFwdArgs f;          // f.depth and f.aux are the forward's outputs (read)
+  float* opa;
 };
 
 hipError_t launch_render_fwd(const RenderFwdArgs& a, int tile, int window, int64_t n_tiles, hipStream_t s);
 hipError_t launch_render_bwd(const RenderBwdArgs& a, int tile, int window, int64_t n_tiles, hipStream_t s);
+hipError_t launch_render_opa(const RenderOpaArgs& a, int tile, int window, int64_t n_tiles, hipStream_t s);
 bool render_supported(int tile, int window);
 
 struct ProjectBwdArgs {

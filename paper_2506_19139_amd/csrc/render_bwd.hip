@@ -64,7 +64,7 @@ __device__ inline float wave_field_sums16(const float* gv, bool mine, int lane) 
   return v1;
 }
 
-template <int TS, int W>
+template <int TS, int W, bool OPA>
 __global__ __launch_bounds__(TS * TS) void k_render_bwd(RenderBwdArgs A) {
   constexpr int NT = TS * TS;
   constexpr int B = NT < 128 ? NT : 128;         // list entries staged per batch
@@ -124,6 +124,19 @@ __global__ __launch_bounds__(TS * TS) void k_render_bwd(RenderBwdArgs A) {
   const float rx = (px + 0.5f - cam.cx) * ifx, ry = (py + 0.5f - cam.cy) * ify;
   const float dn = sqrtf(fmaf(rx, rx, fmaf(ry, ry, 1.f)));
 
+  // ---- opacity at the rendered depth: x at view z s_r on this ray, dL/dalpha_j(x) =
+  //      g_opa prod_{i != j} (1 - alpha_i(x)) = g_opa (1 - O_N) / (1 - alpha_j(x))
+  float s_r = 0.f, gopaP = 0.f;
+  bool opa_on = false;
+  if constexpr (OPA) {
+    if (inside && kgid >= 0) {
+      const float go = A.d_opa[ci.pix_off + pix];
+      s_r = A.out_depth[ci.pix_off + pix] / dn;
+      gopaP = go * (1.f - A.opa[ci.pix_off + pix]);
+      opa_on = go != 0.f;
+    }
+  }
+
   // ---- exact-depth terms of the crossing Gaussian (full mode)
   const bool full = (a.flags & SOF_DEPTH_GRAD_FULL) && !(a.flags & SOF_DEPTH_MEDIAN);
   float cT = 0.f, dq_k = 0.f, dA_k = 0.f, do_k = 0.f;
@@ -164,6 +177,7 @@ __global__ __launch_bounds__(TS * TS) void k_render_bwd(RenderBwdArgs A) {
   float qdq = 0.f, qdo = 0.f, qw = 0.f;
   uint32_t qe = 0u;
   int32_t qg = 0;
+  float qal = 0.f;
   float k_ds = 0.f, k_dA = 0.f;
 
   // Gaussian of list slot `pos`: from the LDS ring while its batch is resident
@@ -216,6 +230,7 @@ __global__ __launch_bounds__(TS * TS) void k_render_bwd(RenderBwdArgs A) {
     qw = w;
     qe = e;
     qg = g;
+    qal = al;
     if (++p.emitted >= p.n_emit) p.done = true;
   };
 
@@ -247,6 +262,14 @@ __global__ __launch_bounds__(TS * TS) void k_render_bwd(RenderBwdArgs A) {
     const float Pdy = P01 * dvx + P11 * dvy + P12;
     const float Pdz = P02 * dvx + P12 * dvy + P22;
     const float Am = aa * q.den;
+    // opacity at the rendered depth, peak in front of x: alpha_j(x) is the blend alpha
+    if constexpr (OPA) {
+      if (opa_on && sstar <= s_r && qal < kAlphaMax) {
+        const float dl = gopaP / (1.f - qal);
+        dq -= 0.5f * qal * dl;
+        dop += dl * qal / r3.y;
+      }
+    }
     const float sA = ds / Am, hA = 0.5f * sA, dq2 = 2.f * dq;
     gv[0] = dq2 * Prx + sA * Pdx;
     gv[1] = dq2 * Pry + sA * Pdy;
@@ -260,6 +283,32 @@ __global__ __launch_bounds__(TS * TS) void k_render_bwd(RenderBwdArgs A) {
     gv[9] = dop;
     gv[10] = gr * w; gv[11] = gg * w; gv[12] = gb * w;
     gv[13] = gnx * w; gv[14] = gny * w; gv[15] = gnz * w;
+    // opacity at the rendered depth, peak beyond x: alpha_j(x) = o exp(-q(x)/2) with
+    // q(x) = u^T P u, u = mu_c - x (x = s_r (dm + delta)); dq/dmu_c = 2 P u, dq/dP_c = u u^T
+    if constexpr (OPA) {
+      if (opa_on && sstar > s_r) {
+        const float dsr = s_r - sstar;
+        const float xs = fmaxf(q.num * iden, 0.f);
+        const float araw = r3.y * exp2f(-(xs + kHalfLog2e * Am * dsr * dsr));
+        const float ax = fminf(kAlphaMax, araw);
+        if (ax >= kAlphaMin && s_r > near_plane && araw < kAlphaMax) {
+          const float dl = gopaP / (1.f - ax);
+          const float dqx = -0.5f * ax * dl, dqx2 = 2.f * dqx;
+          const float mzr = mz - s_r;
+          const float ux = mzr * dmx - s_r * dnx, uy = mzr * dmy - s_r * dny, uz = mzr;
+          gv[0] += dqx2 * (P00 * ux + P01 * uy + P02 * uz);
+          gv[1] += dqx2 * (P01 * ux + P11 * uy + P12 * uz);
+          gv[2] += dqx2 * (P02 * ux + P12 * uy + P22 * uz);
+          gv[3] += dqx * ux * ux;
+          gv[4] += dqx * ux * uy;
+          gv[5] += dqx * ux * uz;
+          gv[6] += dqx * uy * uy;
+          gv[7] += dqx * uy * uz;
+          gv[8] += dqx * uz * uz;
+          gv[9] += dl * ax / r3.y;
+        }
+      }
+    }
   };
 
   // Every lane with a pending Gaussian computes its partials; they are then added
@@ -391,20 +440,25 @@ __global__ __launch_bounds__(TS * TS) void k_render_bwd(RenderBwdArgs A) {
   }
 }
 
-template <int TS>
-static hipError_t launch_bwd_ts(const RenderBwdArgs& a, int window, int64_t n_tiles, hipStream_t s) {
+template <int TS, bool OPA>
+static hipError_t launch_bwd_tso(const RenderBwdArgs& a, int window, int64_t n_tiles, hipStream_t s) {
   const dim3 grid((unsigned)n_tiles), block(TS * TS);
   switch (window) {
-    case 0: hipLaunchKernelGGL((k_render_bwd<TS, 0>), grid, block, 0, s, a); break;
-    case 1: hipLaunchKernelGGL((k_render_bwd<TS, 1>), grid, block, 0, s, a); break;
-    case 2: hipLaunchKernelGGL((k_render_bwd<TS, 2>), grid, block, 0, s, a); break;
-    case 4: hipLaunchKernelGGL((k_render_bwd<TS, 4>), grid, block, 0, s, a); break;
-    case 8: hipLaunchKernelGGL((k_render_bwd<TS, 8>), grid, block, 0, s, a); break;
-    case 16: hipLaunchKernelGGL((k_render_bwd<TS, 16>), grid, block, 0, s, a); break;
-    case 32: hipLaunchKernelGGL((k_render_bwd<TS, 32>), grid, block, 0, s, a); break;
+    case 0: hipLaunchKernelGGL((k_render_bwd<TS, 0, OPA>), grid, block, 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_render_bwd<TS, 1, OPA>), grid, block, 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_render_bwd<TS, 2, OPA>), grid, block, 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_render_bwd<TS, 4, OPA>), grid, block, 0, s, a); break;
+    case 8: hipLaunchKernelGGL((k_render_bwd<TS, 8, OPA>), grid, block, 0, s, a); break;
+    case 16: hipLaunchKernelGGL((k_render_bwd<TS, 16, OPA>), grid, block, 0, s, a); break;
+    case 32: hipLaunchKernelGGL((k_render_bwd<TS, 32, OPA>), grid, block, 0, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+template <int TS>
+static hipError_t launch_bwd_ts(const RenderBwdArgs& a, int window, int64_t n_tiles, hipStream_t s) {
+  return a.d_opa ? launch_bwd_tso<TS, true>(a, window, n_tiles, s) : launch_bwd_tso<TS, false>(a, window, n_tiles, s);
 }
 
 hipError_t launch_render_bwd(const RenderBwdArgs& a, int tile, int window, int64_t n_tiles, hipStream_t s) {

@@ -135,8 +135,13 @@ struct Window {
   }
   // Remove the smallest entry (the head) at the end of the list.
   __device__ inline void pop_front(float& ea, uint32_t& et) {
+    float ek;
+    pop_front(ea, et, ek);
+  }
+  __device__ inline void pop_front(float& ea, uint32_t& et, float& ek) {
     ea = a[0];
     et = t[0];
+    ek = k[0];
     if constexpr (W > 1) {
 #pragma unroll
       for (int i = 0; i < W - 1; ++i) {
@@ -148,11 +153,17 @@ struct Window {
     k[W > 0 ? W - 1 : 0] = __builtin_huge_valf();
     --count;
   }
-  // Feed one candidate.  Returns true with (ea, et) set when an entry leaves the window.
+  // Feed one candidate.  Returns true with (ea, et) set when an entry leaves the window
+  // (ek: its key).
   __device__ inline bool push(float key, float al, uint32_t tag, float& ea, uint32_t& et) {
+    float ek;
+    return push(key, al, tag, ea, et, ek);
+  }
+  __device__ inline bool push(float key, float al, uint32_t tag, float& ea, uint32_t& et, float& ek) {
     if constexpr (W == 0) {
       ea = al;
       et = tag;
+      ek = key;
       return true;
     } else {
       if (count < W) {
@@ -174,10 +185,12 @@ struct Window {
       if (key < k[0]) {
         ea = al;
         et = tag;
+        ek = key;
         return true;
       }
       ea = a[0];
       et = t[0];
+      ek = k[0];
       // drop the head, insert the newcomer after every entry with key <= its key
 #pragma unroll
       for (int i = 0; i < W; ++i) {

@@ -1,0 +1,137 @@
+// Opacity field at the rendered depth (Sec. 3.3, direct opacity-field supervision): for each
+// pixel with a 0.5 crossing, O_N(x) at x = o + t_r d, t_r the depth the forward wrote, over
+// the Gaussians that pixel blends, each evaluated at min(t*, t_r) as in Eq. (12).  Whether a
+// Gaussian peaks in front of x is only known once t_r is, so this is a second pass: it
+// replays the forward's per-pixel order (same tile lists, candidate test and window) and
+// stops after the forward's blend count.  Only products are accumulated (O_N does not
+// depend on the order, App. A.2).
+#include "launch.h"
+#include "render_common.h"
+
+namespace sof {
+
+template <int TS, int W>
+__global__ __launch_bounds__(TS * TS) void k_render_opa(RenderOpaArgs A) {
+  constexpr int NT = TS * TS;
+  constexpr int B = NT < 256 ? NT : 256;
+  __shared__ StageEntry stage[B];
+  __shared__ uint2 srect[B];
+  const RenderFwdArgs& a = A.f;
+  const int tile = blockIdx.x;
+  const int c = find_cam(a.cam_info, a.n_cams, tile);
+  const CamInfo ci = a.cam_info[c];
+  const sof_camera& cam = a.cams[c];
+  const int width = cam.width, height = cam.height;
+  const int lt = tile - ci.tile_off;
+  const int tx = lt % ci.tiles_x, ty = lt / ci.tiles_x;
+  int lx, ly;
+  lane_pixel<TS>((int)threadIdx.x, lx, ly);
+  const int x0 = tx * TS, y0 = ty * TS;
+  const int px = x0 + lx, py = y0 + ly;
+  const int sx = x0 + (lx & ~7), sy = y0 + (ly & ~7);
+  const int sxu = __builtin_amdgcn_readfirstlane(sx), syu = __builtin_amdgcn_readfirstlane(sy);
+  const bool inside = px < width && py < height;
+  const int2 rg = a.ranges[tile];
+  const int64_t cam_base = (int64_t)c * a.n;
+  const float near_plane = a.near_plane;
+
+  // per pixel: the forward's blend count, crossing and depth (as a view z along this ray)
+  const int64_t hw = (int64_t)width * height;
+  const int64_t pix = (int64_t)py * width + px;
+  int n_emit = 0, kgid = -1;
+  float s_r = 0.f;
+  if (inside) {
+    const float* aux = a.aux + kAuxChannels * ci.pix_off;
+    n_emit = __float_as_int(aux[hw + pix]);
+    kgid = __float_as_int(aux[2 * hw + pix]);
+    const float rx = (px + 0.5f - cam.cx) / cam.fx, ry = (py + 0.5f - cam.cy) / cam.fy;
+    const float dn = sqrtf(fmaf(rx, rx, fmaf(ry, ry, 1.f)));
+    s_r = a.depth[ci.pix_off + pix] / dn;
+  }
+  float P = 1.f;                       // prod (1 - alpha_j(x)) over the counted Gaussians
+  int emitted = 0;
+  bool done = !inside || kgid < 0 || n_emit <= 0;
+  Window<W> win;
+  win.init();
+
+  // window payload: key = peak view z s*, a = unclamped o G*, t = bits of A (= d^T P d)
+  auto count = [&](float sstar, float araw, uint32_t abits) {
+    float ax = fminf(kAlphaMax, araw);
+    bool keep = true;                                    // a candidate: alpha >= 1/255, s* > near
+    if (sstar > s_r) {                                   // peak beyond x: evaluate at x
+      const float ds = s_r - sstar;
+      ax = fminf(kAlphaMax, araw * __builtin_amdgcn_exp2f(-kHalfLog2e * __uint_as_float(abits) * ds * ds));
+      keep = ax >= kAlphaMin && s_r > near_plane;
+    }
+    P = keep ? P * (1.f - ax) : P;
+    if (++emitted >= n_emit) done = true;
+  };
+
+  for (int bs = rg.x; bs < rg.y; bs += B) {
+    if (__syncthreads_count(!done) == 0) break;
+    const int i = bs + (int)threadIdx.x;
+    if (threadIdx.x < B && i < rg.y) {
+      const int32_t g = a.gid[a.vals[i]];
+      const int64_t vg = cam_base + g;
+      stage_entry(a.geom, a.rect, vg, x0, y0, 0u, &stage[threadIdx.x], &srect[threadIdx.x]);
+      stage[threadIdx.x].tag = a.geom[4 * vg + 3].w;     // the record's a = dm^T P dm
+    }
+    __syncthreads();
+    const int nb = min(B, rg.y - bs);
+    for (int j = 0; j < nb; ++j) {
+      if (!__any(!done)) break;
+      if (misses_subtile(uniform_rect(srect[j]), sxu, syu)) continue;
+      const StageEntry e = stage[j];
+      const Cand1 c1 = candidate_stage1(e, lx, ly, near_plane);
+      if (!__any(c1.pre && !done)) continue;
+      float key, al;
+      const bool cand = candidate_stage2(e, c1, key, al) && !done;
+      if (!__any(cand)) continue;
+      if (cand) {
+        const float x = fmaxf(c1.q.num * __builtin_amdgcn_rcpf(c1.q.den), 0.f);
+        const float araw = e.o * __builtin_amdgcn_exp2f(-x);
+        float ea, ek;
+        uint32_t et;
+        if (win.push(key, araw, __float_as_uint(e.tag * c1.q.den), ea, et, ek)) count(ek, ea, et);
+      }
+    }
+  }
+  if constexpr (W > 0) {
+    while (!done && win.count > 0) {
+      float ea, ek;
+      uint32_t et;
+      win.pop_front(ea, et, ek);
+      count(ek, ea, et);
+    }
+  }
+  if (!inside) return;
+  A.opa[ci.pix_off + pix] = kgid >= 0 ? 1.f - P : 0.f;
+}
+
+template <int TS>
+static hipError_t launch_opa_ts(const RenderOpaArgs& a, int window, int64_t n_tiles, hipStream_t s) {
+  const dim3 grid((unsigned)n_tiles), block(TS * TS);
+  switch (window) {
+    case 0: hipLaunchKernelGGL((k_render_opa<TS, 0>), grid, block, 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_render_opa<TS, 1>), grid, block, 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_render_opa<TS, 2>), grid, block, 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_render_opa<TS, 4>), grid, block, 0, s, a); break;
+    case 8: hipLaunchKernelGGL((k_render_opa<TS, 8>), grid, block, 0, s, a); break;
+    case 16: hipLaunchKernelGGL((k_render_opa<TS, 16>), grid, block, 0, s, a); break;
+    case 32: hipLaunchKernelGGL((k_render_opa<TS, 32>), grid, block, 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_render_opa(const RenderOpaArgs& a, int tile, int window, int64_t n_tiles, hipStream_t s) {
+  if (n_tiles <= 0) return hipSuccess;
+  switch (tile) {
+    case 8: return launch_opa_ts<8>(a, window, n_tiles, s);
+    case 16: return launch_opa_ts<16>(a, window, n_tiles, s);
+    case 32: return launch_opa_ts<32>(a, window, n_tiles, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace sof

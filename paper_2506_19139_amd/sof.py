@@ -65,8 +65,11 @@ _SIGS = {
                                     ctypes.c_size_t, _P]),
     "sof_render_fwd": (ctypes.c_int, [ctypes.c_int64, _P, _P, ctypes.c_int32, _P, _P, ctypes.c_size_t, _P,
                                       ctypes.c_size_t, _P, _P, _P, _P, _P, _P]),
+    "sof_render_opacity": (ctypes.c_int, [ctypes.c_int64, _P, _P, ctypes.c_int32, _P, _P, ctypes.c_size_t, _P,
+                                          ctypes.c_size_t, _P, _P, _P, _P]),
     "sof_render_bwd": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, _P, _P, ctypes.c_size_t, _P, ctypes.c_size_t,
-                                      _P, _P, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P, _P, _P, _P, _P, _P]),
+                                      _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P, _P, _P, _P,
+                                      _P, _P]),
     "sof_query_workspace_size": (ctypes.c_int, [ctypes.c_int64, _P, ctypes.c_int32, _P, ctypes.c_int64,
                                                 ctypes.c_int64, _SZ, _SZ, _SZ]),
     "sof_opacity_query": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, _P, _P, ctypes.c_int64, ctypes.c_int64,
@@ -222,14 +225,22 @@ def render_fwd(n, cams: Cameras, opts: Options, proj, bins, rgb=None, acc=None, 
                                 _stream()), "sof_render_fwd")
 
 
+def render_opacity(n, cams: Cameras, opts: Options, proj, bins, depth, aux, opacity):
+    o = opts.c_struct()
+    _check(lib().sof_render_opacity(n, cams.hp(), cams.dp(), len(cams), ctypes.byref(o), _ptr(proj), proj.numel(),
+                                    _ptr(bins), bins.numel(), _ptr(depth), _ptr(aux), _ptr(opacity), _stream()),
+           "sof_render_opacity")
+
+
 def render_bwd(g: Gaussians, cams: Cameras, opts: Options, proj, bins, rgb, normal, aux, d_rgb, d_acc, d_depth,
-               d_normal, grads, d_means, d_scales, d_quats, d_opac, d_sh):
+               d_normal, grads, d_means, d_scales, d_quats, d_opac, d_sh, depth=None, opacity=None, d_opacity=None):
     gs, o = g.c_struct(), opts.c_struct()
     _check(lib().sof_render_bwd(ctypes.byref(gs), cams.hp(), cams.dp(), len(cams), ctypes.byref(o), _ptr(proj),
                                 proj.numel(), _ptr(bins), bins.numel(), _ptr(rgb), _ptr(normal), _ptr(aux),
-                                _ptr(d_rgb), _ptr(d_acc), _ptr(d_depth), _ptr(d_normal), _ptr(grads),
-                                grads.numel() if grads is not None else 0, _ptr(d_means), _ptr(d_scales),
-                                _ptr(d_quats), _ptr(d_opac), _ptr(d_sh), _stream()), "sof_render_bwd")
+                                _ptr(d_rgb), _ptr(d_acc), _ptr(d_depth), _ptr(d_normal), _ptr(depth), _ptr(opacity),
+                                _ptr(d_opacity), _ptr(grads), grads.numel() if grads is not None else 0,
+                                _ptr(d_means), _ptr(d_scales), _ptr(d_quats), _ptr(d_opac), _ptr(d_sh), _stream()),
+           "sof_render_bwd")
 
 
 def read_status(buf: torch.Tensor):
@@ -380,14 +391,24 @@ class Rasterizer:
                    out["normal"], out["aux"])
         return out
 
-    def backward(self, g: Gaussians, out, d_rgb=None, d_acc=None, d_depth=None, d_normal=None, grads_out=None):
+    def opacity(self, g: Gaussians, out):
+        """Opacity field at each pixel's rendered depth (second pass after forward); stored in
+        out["opa"] (0 where a pixel has no 0.5 crossing)."""
+        if "opa" not in out:
+            out["opa"] = torch.empty(self.cams.n_pixels, device=self.device)
+        render_opacity(g.n, self.cams, self.opts, self.proj, self.bins, out["depth"], out["aux"], out["opa"])
+        return out["opa"]
+
+    def backward(self, g: Gaussians, out, d_rgb=None, d_acc=None, d_depth=None, d_normal=None, grads_out=None,
+                 d_opa=None):
         if grads_out is None:
             grads_out = dict(means=torch.empty_like(g.means), scales=torch.empty_like(g.scales),
                              quats=torch.empty_like(g.quats), opac=torch.empty_like(g.opac),
                              sh=torch.empty_like(g.sh))
         render_bwd(g, self.cams, self.opts, self.proj, self.bins, out["rgb"], out["normal"], out["aux"], d_rgb, d_acc,
                    d_depth, d_normal, self.grads, grads_out["means"], grads_out["scales"], grads_out["quats"],
-                   grads_out["opac"], grads_out["sh"])
+                   grads_out["opac"], grads_out["sh"], depth=out["depth"] if d_opa is not None else None,
+                   opacity=out.get("opa") if d_opa is not None else None, d_opacity=d_opa)
         return grads_out
 
     def split(self, flat, channels):
