@@ -100,7 +100,8 @@ def _forward_parity(cams, pixels_per_cam, host, cam_ids, scene, window):
     return totals
 
 
-def _directional_fd(scene, cams, pixels_per_cam, weights, cam_ids, grads, window, n_dirs=3, seed=0, h=1e-6):
+def _directional_fd(scene, cams, pixels_per_cam, weights, cam_ids, grads, window, n_dirs=3, seed=0, h=1e-6,
+                    opa=None):
     """Directional derivatives of the oracle's loss (summed over cameras, each evaluated on
     its own sub-scene) against the HIP gradient; returns (hip, fd, groups) for directions
     whose two evaluations lie in the same smooth piece."""
@@ -112,7 +113,7 @@ def _directional_fd(scene, cams, pixels_per_cam, weights, cam_ids, grads, window
     rng = np.random.default_rng(seed)
     out = []
     tries = 0
-    while len(out) < n_dirs and tries < 3 * n_dirs:
+    while len(out) < n_dirs and tries < 4 * n_dirs:
         tries += 1
         # direction: all parameters, geometry only, or appearance only
         groups = [PARAMS, ("means", "scales", "quats"), ("opac", "sh")][len(out) % 3]
@@ -123,11 +124,13 @@ def _directional_fd(scene, cams, pixels_per_cam, weights, cam_ids, grads, window
 
         def loss(sign):
             total, sigs = 0.0, []
-            for oc, loc, pix, wts in zip(ocams, local, pixels_per_cam, weights):
+            for ci, (oc, loc, pix, wts) in enumerate(zip(ocams, local, pixels_per_cam, weights)):
                 arr = {k: (base[k] + sign * h * dirs[k])[loc] for k in PARAMS}
                 sc = O.Scene(arr["means"], arr["scales"], arr["quats"], arr["opac"].reshape(-1), arr["sh"],
                              int(sub["sh_degree"]))
-                lo, sig = O.linear_loss(sc, [oc], window, [pix], [wts], depth_mode="median")
+                ow, od = (None, None) if opa is None else ([opa[0][ci]], [opa[1][ci]])
+                lo, sig = O.linear_loss(sc, [oc], window, [pix], [wts], depth_mode="median", opa_weights=ow,
+                                        opa_depths=od)
                 # the per-Gaussian normal (shortest axis, flipped to face the camera) is piecewise
                 # constant in the parameters: its jumps are discontinuities the order misses
                 used = sorted({int(i) for order, *_ in sig for i in order})
@@ -186,10 +189,12 @@ def _check_directions(pairs, what):
         assert rel <= 1e-3, (what, groups, g, fd, rel)
 
 
-def _run_training_case(scene, cams, tile, window, pixels_per_cam, seed, label):
+def _run_training_case(scene, cams, tile, window, pixels_per_cam, seed, label, opa=False):
     r = sof.Rasterizer(sof.Cameras(cams), sof.Options(tile=tile, window=window))
     g = sof.Gaussians.from_numpy(scene)
     out = r.forward(g)
+    if opa:
+        r.opacity(g, out)
     torch.cuda.synchronize()
     host = {k: v.cpu().numpy() for k, v in out.items()}
     reach = _reach(scene)
@@ -199,15 +204,52 @@ def _run_training_case(scene, cams, tile, window, pixels_per_cam, seed, label):
     bad, unflagged, frag = _forward_parity(cams, pixels_per_cam, host, cam_ids, scene, window)
     assert unflagged == 0, (label, bad, frag)
     weights, d_rgb, d_acc, d_depth, d_nrm = _upstream(cams, pixels_per_cam, seed)
-    grads = r.backward(g, out, d_rgb, d_acc, d_depth, d_nrm)
+    opa_terms, d_opa = None, None
+    if opa:
+        opa_terms, d_opa = _opacity_parity_and_weights(scene, cams, pixels_per_cam, host, cam_ids, window, seed)
+    grads = r.backward(g, out, d_rgb, d_acc, d_depth, d_nrm, d_opa=d_opa)
     torch.cuda.synchronize()
     grads = {k: v.cpu().numpy() for k, v in grads.items()}
     outside = np.ones(len(scene["opac"]), bool)
     outside[np.concatenate(cam_ids)] = False
     for k, v in grads.items():                   # no sampled ray reaches these Gaussians
         assert float(np.abs(v[outside]).max(initial=0.0)) == 0.0, k
-    pairs = _directional_fd(scene, cams, pixels_per_cam, weights, cam_ids, grads, window, seed=seed)
+    # with the opacity term more decisions are piecewise constant (alpha at x against 1/255), so
+    # its directions take a smaller step
+    pairs = _directional_fd(scene, cams, pixels_per_cam, weights, cam_ids, grads, window, seed=seed, opa=opa_terms,
+                            h=1e-7 if opa else 1e-6)
     _check_directions(pairs, label)
+
+
+def _opacity_parity_and_weights(scene, cams, pixels_per_cam, host, cam_ids, window, seed):
+    """Opacity at the rendered depth on the sampled pixels against the oracle, and random
+    upstream weights for it: ([weights per camera], [oracle depths per camera]) for the
+    oracle's loss and the concatenated upstream buffer of the HIP path."""
+    rng = np.random.default_rng(1000 + seed)
+    d_opa = np.zeros(sum(c["width"] * c["height"] for c in cams), np.float32)
+    ws, ds = [], []
+    off, worst, n = 0, 0.0, 0
+    for cam, pixels, ids in zip(cams, pixels_per_cam, cam_ids):
+        sc = O.Scene.from_arrays(**scenes.subset_scene(scene, ids))
+        oc = O.Camera.from_arrays(**cam)
+        v = O.view(sc, oc)
+        w = rng.normal(0.0, 1.0, len(pixels)).astype(np.float32)
+        dep = []
+        for (px, py), wi in zip(pixels, w):
+            res = O.render_pixel(sc, v, px, py, window)
+            on, _ = O.opacity_at_depth(sc, v, px, py, res)
+            i = off + py * cam["width"] + px
+            if on is not None:
+                worst = max(worst, abs(float(host["opa"][i]) - on))
+                n += 1
+            dep.append(res.depth)
+            d_opa[i] += wi
+        ws.append(w.astype(np.float64))
+        ds.append(dep)
+        off += cam["width"] * cam["height"]
+    print(f"  opacity at the rendered depth: {n} sampled pixels with a crossing, worst {worst:.2e}")
+    assert n >= 10 and worst <= 1e-4
+    return (ws, ds), torch.from_numpy(d_opa).cuda()
 
 
 @pytest.fixture(scope="module")
@@ -220,6 +262,14 @@ def test_unbounded_1m_1080p_training_step(unbounded_1m):
     headline launch.  64 sampled pixels: forward parity and three directional derivatives."""
     cam = scenes.circle_camera(0.0, 1920, 1080)
     _run_training_case(unbounded_1m, [cam], 16, 8, [_sample_pixels(cam, 64, 1)], 21, "unbounded 1M 1080p")
+
+
+def test_unbounded_1m_1080p_opacity_term(unbounded_1m):
+    """The same launch with the opacity pass (L_opa): its value on 64 sampled pixels and the
+    directional derivatives of a loss that includes it (depth held at the oracle's)."""
+    cam = scenes.circle_camera(0.0, 1920, 1080)
+    _run_training_case(unbounded_1m, [cam], 16, 8, [_sample_pixels(cam, 64, 3)], 24, "unbounded 1M 1080p + L_opa",
+                       opa=True)
 
 
 def test_unbounded_1m_eight_cameras_training_step(unbounded_1m):
