@@ -83,6 +83,8 @@ def parse():
     ap.add_argument("--no-per-view", action="store_true",
                     help="skip the comparison against one query launch per view")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-opacity-term", action="store_true",
+                    help="skip the training step with the opacity-at-depth term (L_opa)")
     ap.add_argument("--no-levelset", action="store_true",
                     help="skip the level-set query and the binary search")
     ap.add_argument("--no-multiview", action="store_true",
@@ -255,6 +257,46 @@ def levelset_search(qg, pts, qcams, tile, t_exact, stream, steps=8):
                           "ms_per_step": round(tb / steps, 2)}}
 
 
+def opacity_term_step(g, C, opts, rast, out, grads, target, d_acc, d_depth, d_normal, stream, steps):
+    """The headline step plus the paper's opacity supervision: the second pass that evaluates
+    the opacity field at each pixel's rendered depth and the backward with its gradient
+    (upstream 2 lambda (O_N - 0.5) / P, lambda = 0.04 as in the paper's loss weights)."""
+    import torch
+    from paper_2506_19139_amd import sof
+    timer = sof.KernelTimer()
+    t_opa, t_step = [], []
+
+    def step(record):
+        a = [torch.cuda.Event(enable_timing=True) for _ in range(4)] if record else None
+        if record: a[0].record(stream)
+        sof.project(g, C, opts, rast.proj)
+        sof.bin_sort(g.n, C, opts, rast.proj, rast.bins)
+        sof.render_fwd(g.n, C, opts, rast.proj, rast.bins, out["rgb"], out["acc"], out["depth"], out["normal"],
+                       out["aux"])
+        if record: a[1].record(stream)
+        opa = rast.opacity(g, out)
+        if record: a[2].record(stream)
+        d_rgb = torch.sign(out["rgb"] - target) * (1.0 / out["rgb"].numel())
+        d_opa = (opa - 0.5) * (2.0 * 0.04 / opa.numel())
+        rast.backward(g, out, d_rgb, d_acc, d_depth, d_normal, grads_out=grads, d_opa=d_opa)
+        if record:
+            a[3].record(stream)
+            t_opa.append((a[1], a[2]))
+            t_step.append((a[0], a[3]))
+
+    for _ in range(2):
+        step(False)
+    torch.cuda.synchronize()
+    for _ in range(steps):
+        with timer:
+            step(True)
+    torch.cuda.synchronize()
+    ms = lambda v: float(np.mean([x.elapsed_time(y) for x, y in v]))
+    return {"opacity_pass_ms": round(ms(t_opa), 4), "k_render_bwd_ms": round(float(np.mean(timer.ms("render_bwd"))), 4),
+            "step_ms": round(ms(t_step), 4),
+            "workload": "headline step + opacity at the rendered depth (second pass) and its gradient"}
+
+
 # --------------------------------------------------------------------------- GPU
 
 def main():
@@ -372,6 +414,11 @@ def main():
         "per_call_ms": {k: round(v, 4) for k, v in per.items()},
         "roofline": roofline,
     }
+
+    if not args.no_opacity_term:
+        log("step with the opacity term")
+        result["opacity_term"] = opacity_term_step(g, C, opts, rast, out, grads, target, d_acc, d_depth, d_normal,
+                                                   stream, args.steps)
 
     if not args.no_multiview:
         log("multiview step")
