@@ -24,6 +24,8 @@ paper's definitions:
   towards the 0.5 level set; only O > 0.5 or not matters there)
 * opacity field at the rendered depth (L_opa)         -- Sec. 3.3 "Direct Opacity Field
   Supervision"
+* distortion and extent losses                       -- Sec. 3.3 "Distortion Loss", "Extent
+  Loss"; App. C.1, C.2
 
 Readings of passages the paper leaves open (all listed in the design notes):
   R1  A, B, C are written with Sigma^{-1} directly (A = d^T S^-1 d, B = 2 d^T S^-1 (o-mu),
@@ -54,6 +56,9 @@ Readings of passages the paper leaves open (all listed in the design notes):
       O_N(x) over the Gaussians the pixel blends (the paper's first pass accumulates over
       them), each with alpha at t_eval = min(t*_j, t_r) as in Eq. (12); undefined without a
       crossing.  Gradients treat t_r as a constant (as the exact-depth correction).
+  R18 distortion and extent losses: NDC(t) = f (t - n) / ((f - n) t) with n = 0.2, f = 100 on
+      the ray distance (its derivative is the f n / ((f - n) t^2) of App. C.2); the depth of a
+      Gaussian is its t*; sums run over the Gaussians the pixel blends with w = alpha T.
 """
 
 from __future__ import annotations
@@ -596,15 +601,42 @@ def opacity_at_depth(scene: Scene, v: CameraView, px, py, res: PixelResult, t_r=
     return 1.0 - float(np.prod(1.0 - alpha[keep])), [int(i) for i in ids[keep]]
 
 
+NDC_NEAR, NDC_FAR = 0.2, 100.0
+
+
+def ndc(t):
+    """Ray distance -> NDC depth in [0, 1] over [n, f] (R18)."""
+    return NDC_FAR * (t - NDC_NEAR) / ((NDC_FAR - NDC_NEAR) * t)
+
+
+def distortion_extent(scene: Scene, v: CameraView, px, py, res: PixelResult):
+    """Per-pixel distortion loss sum_ij w_i w_j (NDC(t*_i) - NDC(t*_j))^2 and extent loss
+    f n / (f - n) sum_i w_i 2 A_i sqrt(B_i^2 - 4 A_i (C_i - E_i^2)) / B_i^2 over the blended
+    Gaussians (A, B, C of the unit pixel ray, E_i^2 = 2 ln(255 o_i))."""
+    if not res.order:
+        return 0.0, 0.0
+    w = np.asarray(res.weights)
+    d = ndc(np.asarray(res.order_t))
+    dist = float(np.sum(w[:, None] * w[None, :] * (d[:, None] - d[None, :]) ** 2))
+    ids = np.asarray(res.order, dtype=np.int64)
+    dvec, _ = v.cam.pixel_ray(px, py)
+    A, B, C = ray_abc(v.prec[ids], scene.means[ids], v.cam.center, dvec)
+    E2 = 2.0 * np.log(255.0 * scene.opac[ids])
+    ext_i = 2.0 * A * np.sqrt(np.maximum(B * B - 4.0 * A * (C - E2), 0.0)) / (B * B)
+    ext = NDC_FAR * NDC_NEAR / (NDC_FAR - NDC_NEAR) * float(np.sum(w * ext_i))
+    return dist, ext
+
+
 def linear_loss(scene: Scene, cams, window, pixel_lists, weights, depth_mode="exact", bg=(0, 0, 0),
-                opa_weights=None, opa_depths=None):
+                opa_weights=None, opa_depths=None, loss_weights=None):
     """L = sum over cameras and listed pixels of <weights, (rgb, acc, depth, normal)>.
 
     weights[c] is [len(pixel_lists[c]), 8] = (rgb 3, acc, depth, normal 3).  depth_mode
     'exact' uses the 0.5-level-set depth; 'median' uses t*_k (what a detached exact-depth
     correction differentiates to).  opa_weights[c][i] adds that multiple of the opacity at
     the rendered depth (R17; pixels without a crossing add nothing), evaluated at the fixed
-    ray distance opa_depths[c][i] when given (a detached depth).  Returns (loss, signature);
+    ray distance opa_depths[c][i] when given (a detached depth); loss_weights[c][i] weighs
+    the pixel's (distortion, extent) losses (R18).  Returns (loss, signature);
     the signature (emitted ids, crossing index and the ids that count in the opacity per
     pixel) tells whether two evaluations lie in the same smooth piece of the function."""
     loss = 0.0
@@ -616,6 +648,9 @@ def linear_loss(scene: Scene, cams, window, pixel_lists, weights, depth_mode="ex
             dep = r.depth if depth_mode == "exact" else r.median_depth
             vec = np.concatenate([r.rgb, [r.acc, dep], r.normal])
             loss += float(np.dot(vec, w))
+            if loss_weights is not None:
+                dist, ext = distortion_extent(scene, v, px, py, r)
+                loss += loss_weights[c][i][0] * dist + loss_weights[c][i][1] * ext
             used = []
             if opa_weights is not None:
                 t_r = None if opa_depths is None else opa_depths[c][i]
@@ -627,7 +662,7 @@ def linear_loss(scene: Scene, cams, window, pixel_lists, weights, depth_mode="ex
 
 
 def fd_gradient(scene: Scene, cams, window, pixel_lists, weights, depth_mode="exact",
-                names=PARAM_NAMES, h_rel=1e-6, bg=(0, 0, 0), opa_weights=None, opa_depths=None):
+                names=PARAM_NAMES, h_rel=1e-6, bg=(0, 0, 0), opa_weights=None, opa_depths=None, loss_weights=None):
     """Central differences of `linear_loss` for every element of the named parameters.
 
     Returns {name: (grad, smooth)}; smooth[i] is False where the two evaluations fall in
@@ -641,9 +676,9 @@ def fd_gradient(scene: Scene, cams, window, pixel_lists, weights, depth_mode="ex
         for i in range(flat.size):
             h = h_rel * max(1.0, abs(flat[i]))
             lp, sp = linear_loss(_scene_with(scene, name, i, flat[i] + h), cams, window, pixel_lists, weights, depth_mode,
-                                 bg, opa_weights, opa_depths)
+                                 bg, opa_weights, opa_depths, loss_weights)
             lm, sm = linear_loss(_scene_with(scene, name, i, flat[i] - h), cams, window, pixel_lists, weights, depth_mode,
-                                 bg, opa_weights, opa_depths)
+                                 bg, opa_weights, opa_depths, loss_weights)
             g[i] = (lp - lm) / (2.0 * h)
             ok[i] = sp == sm
         out[name] = (g.reshape(base.shape), ok.reshape(base.shape))

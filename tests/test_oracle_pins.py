@@ -549,3 +549,61 @@ def test_opacity_at_depth_equals_the_query_formula_without_termination():
             assert on == pytest.approx(O.opacity_field_view(sc, v, x), abs=1e-12)
             checked += 1
     assert checked >= 20
+
+
+# --------------------------------------------------------------------------- distortion and extent losses (App. C)
+
+def test_ndc_maps_near_and_far_and_has_the_extent_derivative():
+    assert O.ndc(0.2) == pytest.approx(0.0, abs=1e-15) and O.ndc(100.0) == pytest.approx(1.0, abs=1e-15)
+    t, h = 3.7, 1e-6
+    assert (O.ndc(t + h) - O.ndc(t - h)) / (2 * h) == pytest.approx(100.0 * 0.2 / (99.8 * t * t), rel=1e-8)
+
+
+def test_losses_of_one_gaussian_on_the_axis():
+    """One Gaussian: no distortion; on the axis q* = 0 and A = 1/s^2, so the extent of the
+    1/255 contour is s E and the extent loss is f n / (f - n) w s E / D^2, w = o."""
+    D, s, o = 4.0, 0.3, 0.8
+    sc = one_gaussian((0, 0, D), s, o)
+    cam = axis_camera(0.0)
+    v = O.view(sc, cam)
+    r = O.render_pixel(sc, v, 0, 0, 8)
+    dist, ext = O.distortion_extent(sc, v, 0, 0, r)
+    E = math.sqrt(2.0 * math.log(255.0 * o))
+    assert dist == 0.0
+    assert ext == pytest.approx(100.0 * 0.2 / 99.8 * o * s * E / D ** 2, rel=1e-12)
+
+
+def test_distortion_of_two_gaussians_and_its_prefix_form():
+    """Two separated Gaussians on the axis: 2 w1 w2 (NDC(D1) - NDC(D2))^2 with w1 = o1,
+    w2 = o2 (1 - o1); and in a scene the double sum equals the front-to-back prefix form of
+    App. C.1, sum_i w_i (d_i^2 A_{i-1} + DD_{i-1} - 2 d_i D_{i-1}), doubled."""
+    D1, D2, o1, o2 = 3.0, 6.0, 0.7, 0.5
+    sc = O.Scene(np.array([[0, 0, D1], [0, 0, D2]], np.float64), np.full((2, 3), 0.2),
+                 np.array([[1, 0, 0, 0]] * 2, np.float64), np.array([o1, o2], np.float64), np.zeros((2, 1, 3)), 0)
+    cam = axis_camera(0.0)
+    v = O.view(sc, cam)
+    r = O.render_pixel(sc, v, 0, 0, 8)
+    dist, _ = O.distortion_extent(sc, v, 0, 0, r)
+    assert dist == pytest.approx(2 * o1 * o2 * (1 - o1) * (O.ndc(D1) - O.ndc(D2)) ** 2, rel=1e-12)
+    scene = scenes.small_scene(150, seed=4)
+    sc = O.Scene.from_arrays(**scene)
+    oc = O.Camera.from_arrays(**scenes.circle_camera(0.5, 24, 18, radius=3.0))
+    v = O.view(sc, oc)
+    n = 0
+    for py in range(18):
+        for px in range(24):
+            r = O.render_pixel(sc, v, px, py, 8)
+            if len(r.order) < 2:
+                continue
+            dist, _ = O.distortion_extent(sc, v, px, py, r)
+            A = Dm = DD = 0.0
+            pref = 0.0
+            for w, t in zip(r.weights, r.order_t):
+                d = O.ndc(t)
+                pref += w * (d * d * A + DD - 2 * d * Dm)
+                A += w
+                Dm += w * d
+                DD += w * d * d
+            assert dist == pytest.approx(2 * pref, rel=1e-9, abs=1e-15)
+            n += 1
+    assert n >= 50
