@@ -166,11 +166,20 @@ int sof_bin_sort(int64_t n, const sof_camera* h_cams, const sof_camera* d_cams, 
  *   aux    [6,H,W] float32 bits T_end, n_emitted (int32), k (int32 Gaussian index or -1),
  *                               T_k -- needed by sof_render_bwd -- then two int32 work
  *                               counters: list entries tested and candidates found.
+ *   losses [4,H,W]              the per-pixel distortion and extent losses of Sec. 3.3
+ *                               (App. C.1, C.2), then two moments sof_render_bwd needs.  With
+ *                               d = NDC(t*) = f (t* - n) / ((f - n) t*), n = 0.2, f = 100,
+ *                               over the blended Gaussians: distortion = sum_ij w_i w_j
+ *                               (d_i - d_j)^2 = 2 A M with A = sum w, mean mu = sum w d / A
+ *                               and M = sum w (d - mu)^2 (channels 2, 3, accumulated one
+ *                               Gaussian at a time); extent = f n / (f - n) sum w 2 A_i
+ *                               sqrt(B_i^2 - 4 A_i (C_i - E_i^2)) / B_i^2.  NULL: not computed
+ *                               (a kernel without this work runs).
  */
 int sof_render_fwd(int64_t n, const sof_camera* h_cams, const sof_camera* d_cams, int32_t n_cams,
                    const sof_options* opts, const void* proj, size_t proj_bytes, const void* bins,
                    size_t bins_bytes, float* rgb, float* acc, float* depth, float* normal, float* aux,
-                   hipStream_t stream);
+                   float* losses, hipStream_t stream);
 
 /*
  * sof_render_opacity -- Sec. 3.3 (direct opacity-field supervision).
@@ -194,6 +203,9 @@ int sof_render_opacity(int64_t n, const sof_camera* h_cams, const sof_camera* d_
  * zero).  d_opacity (NULL = zero) is the upstream gradient of sof_render_opacity's output;
  * with it, depth and opacity must be the forward's depth and that output.  The depth t_r
  * at which the opacity is evaluated is held constant (like the exact-depth correction).
+ * d_losses [2,H,W] (NULL = zero) is the upstream gradient of the forward's distortion and
+ * extent losses; with it, losses is the forward's [4,H,W] losses output.  Their gradients
+ * follow App. C.1 (dL/dalpha front to back from the stored totals) and C.2.
  * Each pixel's forward order is replayed front to back; suffix sums come from the stored
  * totals.  Writes (overwrites) d_means [n,3], d_scales [n,3], d_quats [n,4], d_opacities
  * [n], d_sh [n,K,3].  `grads` is scratch.  Deterministic: per-instance partials are reduced
@@ -204,9 +216,9 @@ int sof_render_bwd(const sof_gaussians* g, const sof_camera* h_cams, const sof_c
                    const void* bins, size_t bins_bytes, const float* rgb, const float* normal,
                    const float* aux, const float* d_rgb, const float* d_acc, const float* d_depth,
                    const float* d_normal, const float* depth, const float* opacity,
-                   const float* d_opacity, void* grads, size_t grad_bytes, float* d_means,
-                   float* d_scales, float* d_quats, float* d_opacities, float* d_sh,
-                   hipStream_t stream);
+                   const float* d_opacity, const float* losses, const float* d_losses, void* grads,
+                   size_t grad_bytes, float* d_means, float* d_scales, float* d_quats,
+                   float* d_opacities, float* d_sh, hipStream_t stream);
 
 /*
  * Workspace for sof_opacity_query: like sof_workspace_size with the per-view tile lists

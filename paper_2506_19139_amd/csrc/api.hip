@@ -167,12 +167,13 @@ static int fill_fwd_args(int64_t n, const sof_camera* h_cams, const sof_camera* 
 
 int sof_render_fwd(int64_t n, const sof_camera* h_cams, const sof_camera* d_cams, int32_t n_cams,
                    const sof_options* opts, const void* proj, size_t proj_bytes, const void* bins, size_t bins_bytes,
-                   float* rgb, float* acc, float* depth, float* normal, float* aux, hipStream_t stream) {
+                   float* rgb, float* acc, float* depth, float* normal, float* aux, float* losses,
+                   hipStream_t stream) {
   RenderFwdArgs a;
   int64_t n_tiles = 0;
   int st = fill_fwd_args(n, h_cams, d_cams, n_cams, opts, proj, proj_bytes, bins, bins_bytes, &a, &n_tiles);
   if (st) return st;
-  a.rgb = rgb; a.acc = acc; a.depth = depth; a.normal = normal; a.aux = aux;
+  a.rgb = rgb; a.acc = acc; a.depth = depth; a.normal = normal; a.aux = aux; a.losses = losses;
   if (trace_enabled())
     fprintf(stderr, "[sof] render_fwd tiles=%lld tile=%d window=%d\n", (long long)n_tiles, opts->tile, opts->window);
   timing_mark(kTimeRenderFwd, 0, stream);
@@ -201,8 +202,9 @@ int sof_render_bwd(const sof_gaussians* g, const sof_camera* h_cams, const sof_c
                    const sof_options* opts, const void* proj, size_t proj_bytes, const void* bins, size_t bins_bytes,
                    const float* rgb, const float* normal, const float* aux, const float* d_rgb, const float* d_acc,
                    const float* d_depth, const float* d_normal, const float* depth, const float* opacity,
-                   const float* d_opacity, void* grads, size_t grad_bytes, float* d_means, float* d_scales,
-                   float* d_quats, float* d_opacities, float* d_sh, hipStream_t stream) {
+                   const float* d_opacity, const float* losses, const float* d_losses, void* grads,
+                   size_t grad_bytes, float* d_means, float* d_scales, float* d_quats, float* d_opacities,
+                   float* d_sh, hipStream_t stream) {
   int st = check_gauss(g, true);
   if (st) return st;
   RenderBwdArgs b;
@@ -227,6 +229,9 @@ int sof_render_bwd(const sof_gaussians* g, const sof_camera* h_cams, const sof_c
   b.out_depth = d_opacity ? depth : nullptr;
   b.opa = d_opacity ? opacity : nullptr;
   b.d_opa = d_opacity;
+  if (d_losses && !losses) return SOF_E_ARG;
+  b.losses = d_losses ? losses : nullptr;
+  b.d_losses = d_losses;
   if (trace_enabled())
     fprintf(stderr, "[sof] render_bwd tiles=%lld tile=%d window=%d\n", (long long)n_tiles, opts->tile, opts->window);
   timing_mark(kTimeRenderBwd, 0, stream);

@@ -47,6 +47,7 @@ struct RenderFwdArgs {
   float* depth;
   float* normal;
   float* aux;
+  float* losses;            // [4, P]: distortion, extent, sum w d, sum w d^2 (null: off)
 };
 
 struct RenderBwdArgs {
@@ -63,6 +64,9 @@ struct RenderBwdArgs {
   const float* out_depth;
   const float* opa;
   const float* d_opa;
+  // distortion and extent losses: the forward's [4, P] output and upstream [2, P] (null: off)
+  const float* losses;
+  const float* d_losses;
 };
 
 struct RenderOpaArgs {

@@ -64,7 +64,7 @@ __device__ inline float wave_field_sums16(const float* gv, bool mine, int lane) 
   return v1;
 }
 
-template <int TS, int W, bool OPA>
+template <int TS, int W, bool EXT>
 __global__ __launch_bounds__(TS * TS) void k_render_bwd(RenderBwdArgs A) {
   constexpr int NT = TS * TS;
   constexpr int B = NT < 128 ? NT : 128;         // list entries staged per batch
@@ -128,12 +128,32 @@ __global__ __launch_bounds__(TS * TS) void k_render_bwd(RenderBwdArgs A) {
   //      g_opa prod_{i != j} (1 - alpha_i(x)) = g_opa (1 - O_N) / (1 - alpha_j(x))
   float s_r = 0.f, gopaP = 0.f;
   bool opa_on = false;
-  if constexpr (OPA) {
-    if (inside && kgid >= 0) {
+  if constexpr (EXT) {
+    if (A.d_opa && inside && kgid >= 0) {
       const float go = A.d_opa[ci.pix_off + pix];
       s_r = A.out_depth[ci.pix_off + pix] / dn;
       gopaP = go * (1.f - A.opa[ci.pix_off + pix]);
       opa_on = go != 0.f;
+    }
+  }
+
+  // ---- distortion and extent losses: upstream gradients, the forward's totals A = sum w,
+  //      mean mu and central moment M = sum w (d - mu)^2 of d = NDC(t*), E = sum w e, and
+  //      running prefixes of w (d - mu)^2 and w e
+  constexpr float kKappa = kNdcFar * kNdcNear / (kNdcFar - kNdcNear);
+  float g_dist = 0.f, g_ext = 0.f, Atot = 0.f, mu = 0.f, Mtot = 0.f, Etot = 0.f;
+  float Mp = 0.f, Ep = 0.f;
+  bool loss_on = false;
+  if constexpr (EXT) {
+    if (A.d_losses && inside) {
+      const float* L = A.losses + kLossChannels * ci.pix_off;
+      g_dist = A.d_losses[2 * ci.pix_off + pix];
+      g_ext = A.d_losses[2 * ci.pix_off + hw + pix];
+      Atot = 1.f - T_end;
+      Etot = L[hw + pix] / kKappa;
+      mu = L[2 * hw + pix];
+      Mtot = L[3 * hw + pix];
+      loss_on = g_dist != 0.f || g_ext != 0.f;
     }
   }
 
@@ -177,7 +197,7 @@ __global__ __launch_bounds__(TS * TS) void k_render_bwd(RenderBwdArgs A) {
   float qdq = 0.f, qdo = 0.f, qw = 0.f;
   uint32_t qe = 0u;
   int32_t qg = 0;
-  float qal = 0.f;
+  float qal = 0.f, qT = 0.f;
   float k_ds = 0.f, k_dA = 0.f;
 
   // Gaussian of list slot `pos`: from the LDS ring while its batch is resident
@@ -231,6 +251,7 @@ __global__ __launch_bounds__(TS * TS) void k_render_bwd(RenderBwdArgs A) {
     qe = e;
     qg = g;
     qal = al;
+    qT = Tj;
     if (++p.emitted >= p.n_emit) p.done = true;
   };
 
@@ -247,8 +268,8 @@ __global__ __launch_bounds__(TS * TS) void k_render_bwd(RenderBwdArgs A) {
     const float mz = r3.x, aa = r3.w;
     const float iden = 1.f / q.den;
     const float sstar = mz * (1.f + q.b) * iden;
-    const float ds = crossing ? k_ds : 0.f;
-    const float dA = crossing ? k_dA : 0.f;
+    float ds = crossing ? k_ds : 0.f;
+    float dA = crossing ? k_dA : 0.f;
     const float dnx = dx * ifx, dny = dy * ify;
     const float dmx = p1.z, dmy = p1.w;
     const float dvx = dmx + dnx, dvy = dmy + dny;               // d = (dvx, dvy, 1)
@@ -262,8 +283,41 @@ __global__ __launch_bounds__(TS * TS) void k_render_bwd(RenderBwdArgs A) {
     const float Pdy = P01 * dvx + P11 * dvy + P12;
     const float Pdz = P02 * dvx + P12 * dvy + P22;
     const float Am = aa * q.den;
+    // distortion and extent losses (App. C.1, C.2), in blend order: dL/dalpha through the
+    // weights (prefix sums from the running totals), plus the direct terms of d = NDC(t*)
+    // and of the extent e = sqrt((E^2 - q*) / A) / (|d~| s*^2)
+    if constexpr (EXT) {
+      if (loss_on) {
+        const float t = dn * sstar;
+        const float d = kNdcFar * (t - kNdcNear) / ((kNdcFar - kNdcNear) * t);
+        const float ndcp = kKappa / (t * t);
+        const float Tn = qT * (1.f - qal);
+        // L_dist = sum_ij w_i w_j (d_i - d_j)^2: dL/dw_k = 2 (A (d_k - mu)^2 + M), and the
+        // suffix sum_{i>k} w_i dL/dw_i = 2 (A (M - prefix_k) + M (A - A_k))
+        const float dc = d - mu;
+        const float cd = 2.f * (Atot * dc * dc + Mtot);
+        Mp = fmaf(w * dc, dc, Mp);
+        const float Sd = 2.f * (Atot * (Mtot - Mp) + Mtot * (Atot - (1.f - Tn)));
+        float dal_x = g_dist * (cd * qT - Sd / (1.f - qal));
+        ds += g_dist * 4.f * w * Atot * dc * ndcp * dn;                   // dL/dd_k = 4 w_k A (d_k - mu)
+        const float qs = fmaxf(q.num * iden, 0.f) * (2.f * kLn2);
+        const float u = fmaxf(2.f * logf(255.f * r3.y) - qs, 1e-12f);
+        const float e = sqrtf(u / Am) / (dn * sstar * sstar);
+        Ep = fmaf(w, e, Ep);
+        dal_x += g_ext * kKappa * (e * qT - (Etot - Ep) / (1.f - qal));
+        const float ce = g_ext * kKappa * w;
+        dq -= ce * e / (2.f * u);
+        dA -= ce * e / (2.f * Am);
+        ds -= ce * 2.f * e / sstar;
+        dop += ce * e / (u * r3.y);
+        if (qal < kAlphaMax) {
+          dq -= 0.5f * qal * dal_x;
+          dop += dal_x * qal / r3.y;
+        }
+      }
+    }
     // opacity at the rendered depth, peak in front of x: alpha_j(x) is the blend alpha
-    if constexpr (OPA) {
+    if constexpr (EXT) {
       if (opa_on && sstar <= s_r && qal < kAlphaMax) {
         const float dl = gopaP / (1.f - qal);
         dq -= 0.5f * qal * dl;
@@ -285,7 +339,7 @@ __global__ __launch_bounds__(TS * TS) void k_render_bwd(RenderBwdArgs A) {
     gv[13] = gnx * w; gv[14] = gny * w; gv[15] = gnz * w;
     // opacity at the rendered depth, peak beyond x: alpha_j(x) = o exp(-q(x)/2) with
     // q(x) = u^T P u, u = mu_c - x (x = s_r (dm + delta)); dq/dmu_c = 2 P u, dq/dP_c = u u^T
-    if constexpr (OPA) {
+    if constexpr (EXT) {
       if (opa_on && sstar > s_r) {
         const float dsr = s_r - sstar;
         const float xs = fmaxf(q.num * iden, 0.f);
@@ -440,17 +494,17 @@ __global__ __launch_bounds__(TS * TS) void k_render_bwd(RenderBwdArgs A) {
   }
 }
 
-template <int TS, bool OPA>
+template <int TS, bool EXT>
 static hipError_t launch_bwd_tso(const RenderBwdArgs& a, int window, int64_t n_tiles, hipStream_t s) {
   const dim3 grid((unsigned)n_tiles), block(TS * TS);
   switch (window) {
-    case 0: hipLaunchKernelGGL((k_render_bwd<TS, 0, OPA>), grid, block, 0, s, a); break;
-    case 1: hipLaunchKernelGGL((k_render_bwd<TS, 1, OPA>), grid, block, 0, s, a); break;
-    case 2: hipLaunchKernelGGL((k_render_bwd<TS, 2, OPA>), grid, block, 0, s, a); break;
-    case 4: hipLaunchKernelGGL((k_render_bwd<TS, 4, OPA>), grid, block, 0, s, a); break;
-    case 8: hipLaunchKernelGGL((k_render_bwd<TS, 8, OPA>), grid, block, 0, s, a); break;
-    case 16: hipLaunchKernelGGL((k_render_bwd<TS, 16, OPA>), grid, block, 0, s, a); break;
-    case 32: hipLaunchKernelGGL((k_render_bwd<TS, 32, OPA>), grid, block, 0, s, a); break;
+    case 0: hipLaunchKernelGGL((k_render_bwd<TS, 0, EXT>), grid, block, 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_render_bwd<TS, 1, EXT>), grid, block, 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_render_bwd<TS, 2, EXT>), grid, block, 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_render_bwd<TS, 4, EXT>), grid, block, 0, s, a); break;
+    case 8: hipLaunchKernelGGL((k_render_bwd<TS, 8, EXT>), grid, block, 0, s, a); break;
+    case 16: hipLaunchKernelGGL((k_render_bwd<TS, 16, EXT>), grid, block, 0, s, a); break;
+    case 32: hipLaunchKernelGGL((k_render_bwd<TS, 32, EXT>), grid, block, 0, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -458,7 +512,8 @@ static hipError_t launch_bwd_tso(const RenderBwdArgs& a, int window, int64_t n_t
 
 template <int TS>
 static hipError_t launch_bwd_ts(const RenderBwdArgs& a, int window, int64_t n_tiles, hipStream_t s) {
-  return a.d_opa ? launch_bwd_tso<TS, true>(a, window, n_tiles, s) : launch_bwd_tso<TS, false>(a, window, n_tiles, s);
+  const bool ext = a.d_opa || a.d_losses;
+  return ext ? launch_bwd_tso<TS, true>(a, window, n_tiles, s) : launch_bwd_tso<TS, false>(a, window, n_tiles, s);
 }
 
 hipError_t launch_render_bwd(const RenderBwdArgs& a, int tile, int window, int64_t n_tiles, hipStream_t s) {

@@ -12,15 +12,18 @@ namespace sof {
 
 struct PixFwd {
   float T, r, g, b, nx, ny, nz, Tk;
+  float A, mu, M, E;         // losses only: sum w, weighted mean and central second moment of
+                             // d = NDC(t*) (updated one Gaussian at a time), sum w extent
   int n_emit, k, walked, cands;
   bool done;
 };
 
-__device__ inline void blend(PixFwd& p, float alpha, uint32_t gid, const float4* app, int64_t cam_base) {
+// Returns the blend weight (0 when the Gaussian was not blended).
+__device__ inline float blend(PixFwd& p, float alpha, uint32_t gid, const float4* app, int64_t cam_base) {
   const float test_T = p.T * (1.f - alpha);
   if (test_T < kTMin) {
     p.done = true;
-    return;
+    return 0.f;
   }
   const float w = alpha * p.T;
   const float4 c = app[2 * (cam_base + gid)];
@@ -37,9 +40,35 @@ __device__ inline void blend(PixFwd& p, float alpha, uint32_t gid, const float4*
   }
   p.T = test_T;
   ++p.n_emit;
+  return w;
+}
+
+// Distortion and extent terms of one blended Gaussian (Sec. 3.3; App. C.1, C.2): its NDC
+// depth d = NDC(t*) and the extent e = eps / t*^2 of its 1/255 contour along the ray,
+// eps = sqrt((E^2 - q*) / A) on the unit ray; in the stored view-z units
+// e = sqrt((E^2 - q*) / A_s) / (|d~| s*^2) with A_s = d~^T P d~.
+__device__ inline void loss_terms(PixFwd& p, float w, float sstar, uint32_t gid, const float4* geom, int64_t cam_base,
+                                  int px, int py, float dn) {
+  const int64_t vg = cam_base + gid;
+  const float4 r0 = geom[4 * vg], r1 = geom[4 * vg + 1], r2 = geom[4 * vg + 2], r3 = geom[4 * vg + 3];
+  const float2 d2 = pixel_offset(r0, px, py);
+  const Quad q = quad_terms(r1.x, r1.y, r1.z, r1.w, r2.x, r2.y, r2.z, r2.w, d2.x, d2.y);
+  const float qs = fmaxf(q.num / q.den, 0.f) * (2.f * kLn2);          // q*
+  const float u = fmaxf(2.f * logf(255.f * r3.y) - qs, 0.f);          // E^2 - q*
+  const float e = sqrtf(u / (r3.w * q.den)) / (dn * sstar * sstar);
+  const float t = dn * sstar;
+  const float d = kNdcFar * (t - kNdcNear) / ((kNdcFar - kNdcNear) * t);
+  // weighted running mean and second moment (numerically stable; the distortion
+  // sum_ij w_i w_j (d_i - d_j)^2 = 2 A sum w (d - mean)^2 would cancel as 2 (A DD - D^2))
+  p.A += w;
+  const float delta = d - p.mu;
+  p.mu = fmaf(w / p.A, delta, p.mu);
+  p.M = fmaf(w * delta, d - p.mu, p.M);
+  p.E = fmaf(w, e, p.E);
 }
 
 // Depth of the crossing Gaussian and the per-pixel output writes.
+template <bool LOSS>
 __device__ inline void write_pixel(const RenderFwdArgs& a, const PixFwd& p, const sof_camera& cam, const CamInfo& ci,
                                    int64_t cam_base, int px, int py) {
   const int width = cam.width, height = cam.height;
@@ -89,9 +118,17 @@ __device__ inline void write_pixel(const RenderFwdArgs& a, const PixFwd& p, cons
     o[4 * hw + pix] = __int_as_float(p.walked);
     o[5 * hw + pix] = __int_as_float(p.cands);
   }
+  if constexpr (LOSS) {
+    // distortion sum_ij w_i w_j (d_i - d_j)^2 = 2 A M; extent f n / (f - n) sum w e
+    float* o = a.losses + kLossChannels * ci.pix_off;
+    o[pix] = 2.f * p.A * p.M;
+    o[hw + pix] = kNdcFar * kNdcNear / (kNdcFar - kNdcNear) * p.E;
+    o[2 * hw + pix] = p.mu;
+    o[3 * hw + pix] = p.M;
+  }
 }
 
-template <int TS, int W>
+template <int TS, int W, bool LOSS>
 __global__ __launch_bounds__(TS * TS) void k_render_fwd(RenderFwdArgs a) {
   constexpr int NT = TS * TS;
   constexpr int B = NT < 256 ? NT : 256;         // list entries staged per batch
@@ -117,6 +154,12 @@ __global__ __launch_bounds__(TS * TS) void k_render_fwd(RenderFwdArgs a) {
 
   PixFwd p;
   p.T = 1.f; p.r = p.g = p.b = 0.f; p.nx = p.ny = p.nz = 0.f; p.Tk = 0.f; p.n_emit = 0; p.k = -1;
+  p.A = p.mu = p.M = p.E = 0.f;
+  float dn = 1.f;
+  if constexpr (LOSS) {
+    const float rx = (px + 0.5f - cam.cx) / cam.fx, ry = (py + 0.5f - cam.cy) / cam.fy;
+    dn = sqrtf(fmaf(rx, rx, fmaf(ry, ry, 1.f)));
+  }
   p.walked = 0; p.cands = 0;
   p.done = !inside;
   Window<W> win;
@@ -143,38 +186,51 @@ __global__ __launch_bounds__(TS * TS) void k_render_fwd(RenderFwdArgs a) {
       if (!__any(cand)) continue;
       if (cand) {
         ++p.cands;
-        float ea;
+        float ea, ek;
         uint32_t et;
-        if (win.push(key, al, __float_as_uint(e.tag), ea, et)) blend(p, ea, et, a.app, cam_base);
+        if (win.push(key, al, __float_as_uint(e.tag), ea, et, ek)) {
+          const float w = blend(p, ea, et, a.app, cam_base);
+          if constexpr (LOSS) {
+            if (w > 0.f) loss_terms(p, w, ek, et, a.geom, cam_base, px, py, dn);
+          }
+        }
       }
     }
   }
   if constexpr (W > 0) {
     while (!p.done && win.count > 0) {
-      float ea;
+      float ea, ek;
       uint32_t et;
-      win.pop_front(ea, et);
-      blend(p, ea, et, a.app, cam_base);
+      win.pop_front(ea, et, ek);
+      const float w = blend(p, ea, et, a.app, cam_base);
+      if constexpr (LOSS) {
+        if (w > 0.f) loss_terms(p, w, ek, et, a.geom, cam_base, px, py, dn);
+      }
     }
   }
   if (!inside) return;
-  write_pixel(a, p, cam, ci, cam_base, px, py);
+  write_pixel<LOSS>(a, p, cam, ci, cam_base, px, py);
+}
+
+template <int TS, bool LOSS>
+static hipError_t launch_fwd_tsl(const RenderFwdArgs& a, int window, int64_t n_tiles, hipStream_t s) {
+  const dim3 grid((unsigned)n_tiles), block(TS * TS);
+  switch (window) {
+    case 0: hipLaunchKernelGGL((k_render_fwd<TS, 0, LOSS>), grid, block, 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_render_fwd<TS, 1, LOSS>), grid, block, 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_render_fwd<TS, 2, LOSS>), grid, block, 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_render_fwd<TS, 4, LOSS>), grid, block, 0, s, a); break;
+    case 8: hipLaunchKernelGGL((k_render_fwd<TS, 8, LOSS>), grid, block, 0, s, a); break;
+    case 16: hipLaunchKernelGGL((k_render_fwd<TS, 16, LOSS>), grid, block, 0, s, a); break;
+    case 32: hipLaunchKernelGGL((k_render_fwd<TS, 32, LOSS>), grid, block, 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 template <int TS>
 static hipError_t launch_fwd_ts(const RenderFwdArgs& a, int window, int64_t n_tiles, hipStream_t s) {
-  const dim3 grid((unsigned)n_tiles), block(TS * TS);
-  switch (window) {
-    case 0: hipLaunchKernelGGL((k_render_fwd<TS, 0>), grid, block, 0, s, a); break;
-    case 1: hipLaunchKernelGGL((k_render_fwd<TS, 1>), grid, block, 0, s, a); break;
-    case 2: hipLaunchKernelGGL((k_render_fwd<TS, 2>), grid, block, 0, s, a); break;
-    case 4: hipLaunchKernelGGL((k_render_fwd<TS, 4>), grid, block, 0, s, a); break;
-    case 8: hipLaunchKernelGGL((k_render_fwd<TS, 8>), grid, block, 0, s, a); break;
-    case 16: hipLaunchKernelGGL((k_render_fwd<TS, 16>), grid, block, 0, s, a); break;
-    case 32: hipLaunchKernelGGL((k_render_fwd<TS, 32>), grid, block, 0, s, a); break;
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
+  return a.losses ? launch_fwd_tsl<TS, true>(a, window, n_tiles, s) : launch_fwd_tsl<TS, false>(a, window, n_tiles, s);
 }
 
 bool render_supported(int tile, int window) {

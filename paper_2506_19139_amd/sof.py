@@ -26,6 +26,7 @@ SOF_QUERY_REUSE = 1 << 4
 
 WINDOWS = (0, 1, 2, 4, 8, 16, 32)
 AUX_CHANNELS = 6      # T_end, n_emitted, k, T_k, entries tested, candidates
+LOSS_CHANNELS = 4     # distortion, extent, sum w d, sum w d^2
 TILES = (8, 16, 32)
 
 
@@ -64,12 +65,12 @@ _SIGS = {
     "sof_bin_sort": (ctypes.c_int, [ctypes.c_int64, _P, _P, ctypes.c_int32, _P, _P, ctypes.c_size_t, _P,
                                     ctypes.c_size_t, _P]),
     "sof_render_fwd": (ctypes.c_int, [ctypes.c_int64, _P, _P, ctypes.c_int32, _P, _P, ctypes.c_size_t, _P,
-                                      ctypes.c_size_t, _P, _P, _P, _P, _P, _P]),
+                                      ctypes.c_size_t, _P, _P, _P, _P, _P, _P, _P]),
     "sof_render_opacity": (ctypes.c_int, [ctypes.c_int64, _P, _P, ctypes.c_int32, _P, _P, ctypes.c_size_t, _P,
                                           ctypes.c_size_t, _P, _P, _P, _P]),
     "sof_render_bwd": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, _P, _P, ctypes.c_size_t, _P, ctypes.c_size_t,
-                                      _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P, _P, _P, _P,
-                                      _P, _P]),
+                                      _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P, _P,
+                                      _P, _P, _P, _P]),
     "sof_query_workspace_size": (ctypes.c_int, [ctypes.c_int64, _P, ctypes.c_int32, _P, ctypes.c_int64,
                                                 ctypes.c_int64, _SZ, _SZ, _SZ]),
     "sof_opacity_query": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, _P, _P, ctypes.c_int64, ctypes.c_int64,
@@ -218,11 +219,12 @@ def bin_sort(n, cams: Cameras, opts: Options, proj, bins):
                               _ptr(bins), bins.numel(), _stream()), "sof_bin_sort")
 
 
-def render_fwd(n, cams: Cameras, opts: Options, proj, bins, rgb=None, acc=None, depth=None, normal=None, aux=None):
+def render_fwd(n, cams: Cameras, opts: Options, proj, bins, rgb=None, acc=None, depth=None, normal=None, aux=None,
+               losses=None):
     o = opts.c_struct()
     _check(lib().sof_render_fwd(n, cams.hp(), cams.dp(), len(cams), ctypes.byref(o), _ptr(proj), proj.numel(),
                                 _ptr(bins), bins.numel(), _ptr(rgb), _ptr(acc), _ptr(depth), _ptr(normal), _ptr(aux),
-                                _stream()), "sof_render_fwd")
+                                _ptr(losses), _stream()), "sof_render_fwd")
 
 
 def render_opacity(n, cams: Cameras, opts: Options, proj, bins, depth, aux, opacity):
@@ -233,12 +235,14 @@ def render_opacity(n, cams: Cameras, opts: Options, proj, bins, depth, aux, opac
 
 
 def render_bwd(g: Gaussians, cams: Cameras, opts: Options, proj, bins, rgb, normal, aux, d_rgb, d_acc, d_depth,
-               d_normal, grads, d_means, d_scales, d_quats, d_opac, d_sh, depth=None, opacity=None, d_opacity=None):
+               d_normal, grads, d_means, d_scales, d_quats, d_opac, d_sh, depth=None, opacity=None, d_opacity=None,
+               losses=None, d_losses=None):
     gs, o = g.c_struct(), opts.c_struct()
     _check(lib().sof_render_bwd(ctypes.byref(gs), cams.hp(), cams.dp(), len(cams), ctypes.byref(o), _ptr(proj),
                                 proj.numel(), _ptr(bins), bins.numel(), _ptr(rgb), _ptr(normal), _ptr(aux),
                                 _ptr(d_rgb), _ptr(d_acc), _ptr(d_depth), _ptr(d_normal), _ptr(depth), _ptr(opacity),
-                                _ptr(d_opacity), _ptr(grads), grads.numel() if grads is not None else 0,
+                                _ptr(d_opacity), _ptr(losses), _ptr(d_losses), _ptr(grads),
+                                grads.numel() if grads is not None else 0,
                                 _ptr(d_means), _ptr(d_scales), _ptr(d_quats), _ptr(d_opac), _ptr(d_sh), _stream()),
            "sof_render_bwd")
 
@@ -384,11 +388,15 @@ class Rasterizer:
         return dict(rgb=torch.empty(3 * P, device=dev), acc=torch.empty(P, device=dev), depth=torch.empty(P, device=dev),
                     normal=torch.empty(3 * P, device=dev), aux=torch.empty(AUX_CHANNELS * P, device=dev))
 
-    def forward(self, g: Gaussians, out=None):
+    def forward(self, g: Gaussians, out=None, losses=False):
+        """Render; with losses=True also the per-pixel distortion and extent losses in
+        out["losses"] ([4, P]: distortion, extent, and two sums the backward reads)."""
         self.prepare(g)
         out = out or self.alloc_outputs()
+        if losses and "losses" not in out:
+            out["losses"] = torch.empty(LOSS_CHANNELS * self.cams.n_pixels, device=self.device)
         render_fwd(g.n, self.cams, self.opts, self.proj, self.bins, out["rgb"], out["acc"], out["depth"],
-                   out["normal"], out["aux"])
+                   out["normal"], out["aux"], out["losses"] if losses else None)
         return out
 
     def opacity(self, g: Gaussians, out):
@@ -400,7 +408,9 @@ class Rasterizer:
         return out["opa"]
 
     def backward(self, g: Gaussians, out, d_rgb=None, d_acc=None, d_depth=None, d_normal=None, grads_out=None,
-                 d_opa=None):
+                 d_opa=None, d_losses=None):
+        """Gradients of a loss with upstream d_rgb, d_acc, d_depth, d_normal, d_opa (of
+        out["opa"]) and d_losses ([2, P], of the distortion and extent rows of out["losses"])."""
         if grads_out is None:
             grads_out = dict(means=torch.empty_like(g.means), scales=torch.empty_like(g.scales),
                              quats=torch.empty_like(g.quats), opac=torch.empty_like(g.opac),
@@ -408,7 +418,8 @@ class Rasterizer:
         render_bwd(g, self.cams, self.opts, self.proj, self.bins, out["rgb"], out["normal"], out["aux"], d_rgb, d_acc,
                    d_depth, d_normal, self.grads, grads_out["means"], grads_out["scales"], grads_out["quats"],
                    grads_out["opac"], grads_out["sh"], depth=out["depth"] if d_opa is not None else None,
-                   opacity=out.get("opa") if d_opa is not None else None, d_opacity=d_opa)
+                   opacity=out.get("opa") if d_opa is not None else None, d_opacity=d_opa,
+                   losses=out.get("losses") if d_losses is not None else None, d_losses=d_losses)
         return grads_out
 
     def split(self, flat, channels):
