@@ -101,7 +101,7 @@ def _forward_parity(cams, pixels_per_cam, host, cam_ids, scene, window):
 
 
 def _directional_fd(scene, cams, pixels_per_cam, weights, cam_ids, grads, window, n_dirs=3, seed=0, h=1e-6,
-                    opa=None):
+                    opa=None, lw=None):
     """Directional derivatives of the oracle's loss (summed over cameras, each evaluated on
     its own sub-scene) against the HIP gradient; returns (hip, fd, groups) for directions
     whose two evaluations lie in the same smooth piece."""
@@ -130,7 +130,7 @@ def _directional_fd(scene, cams, pixels_per_cam, weights, cam_ids, grads, window
                              int(sub["sh_degree"]))
                 ow, od = (None, None) if opa is None else ([opa[0][ci]], [opa[1][ci]])
                 lo, sig = O.linear_loss(sc, [oc], window, [pix], [wts], depth_mode="median", opa_weights=ow,
-                                        opa_depths=od)
+                                        opa_depths=od, loss_weights=None if lw is None else [lw[ci]])
                 # the per-Gaussian normal (shortest axis, flipped to face the camera) is piecewise
                 # constant in the parameters: its jumps are discontinuities the order misses
                 used = sorted({int(i) for order, *_ in sig for i in order})
@@ -192,7 +192,7 @@ def _check_directions(pairs, what):
 def _run_training_case(scene, cams, tile, window, pixels_per_cam, seed, label, opa=False):
     r = sof.Rasterizer(sof.Cameras(cams), sof.Options(tile=tile, window=window))
     g = sof.Gaussians.from_numpy(scene)
-    out = r.forward(g)
+    out = r.forward(g, losses=opa)
     if opa:
         r.opacity(g, out)
     torch.cuda.synchronize()
@@ -204,10 +204,11 @@ def _run_training_case(scene, cams, tile, window, pixels_per_cam, seed, label, o
     bad, unflagged, frag = _forward_parity(cams, pixels_per_cam, host, cam_ids, scene, window)
     assert unflagged == 0, (label, bad, frag)
     weights, d_rgb, d_acc, d_depth, d_nrm = _upstream(cams, pixels_per_cam, seed)
-    opa_terms, d_opa = None, None
+    opa_terms, d_opa, lw, d_losses = None, None, None, None
     if opa:
         opa_terms, d_opa = _opacity_parity_and_weights(scene, cams, pixels_per_cam, host, cam_ids, window, seed)
-    grads = r.backward(g, out, d_rgb, d_acc, d_depth, d_nrm, d_opa=d_opa)
+        lw, d_losses = _loss_parity_and_weights(scene, cams, pixels_per_cam, host, cam_ids, window, seed)
+    grads = r.backward(g, out, d_rgb, d_acc, d_depth, d_nrm, d_opa=d_opa, d_losses=d_losses)
     torch.cuda.synchronize()
     grads = {k: v.cpu().numpy() for k, v in grads.items()}
     outside = np.ones(len(scene["opac"]), bool)
@@ -217,8 +218,35 @@ def _run_training_case(scene, cams, tile, window, pixels_per_cam, seed, label, o
     # with the opacity term more decisions are piecewise constant (alpha at x against 1/255), so
     # its directions take a smaller step
     pairs = _directional_fd(scene, cams, pixels_per_cam, weights, cam_ids, grads, window, seed=seed, opa=opa_terms,
-                            h=1e-7 if opa else 1e-6)
+                            lw=lw, h=1e-7 if opa else 1e-6)
     _check_directions(pairs, label)
+
+
+def _loss_parity_and_weights(scene, cams, pixels_per_cam, host, cam_ids, window, seed):
+    """Distortion and extent losses on the sampled pixels against the oracle, and random
+    upstream weights for them (oracle layout [n, 2] per camera; HIP layout [2, P])."""
+    rng = np.random.default_rng(2000 + seed)
+    P = sum(c["width"] * c["height"] for c in cams)
+    d_l = np.zeros((2, P), np.float32)
+    out, worst, off = [], 0.0, 0
+    L = host["losses"].reshape(sof.LOSS_CHANNELS, P)
+    for cam, pixels, ids in zip(cams, pixels_per_cam, cam_ids):
+        sc = O.Scene.from_arrays(**scenes.subset_scene(scene, ids))
+        oc = O.Camera.from_arrays(**cam)
+        v = O.view(sc, oc)
+        w = (rng.normal(0.0, 1.0, (len(pixels), 2)) * np.array([20.0, 1.0])).astype(np.float32)
+        for (px, py), wi in zip(pixels, w):
+            res = O.render_pixel(sc, v, px, py, window)
+            dist, ext = O.distortion_extent(sc, v, px, py, res)
+            i = off + py * cam["width"] + px
+            for c, ref in enumerate((dist, ext)):
+                worst = max(worst, abs(float(L[c, i]) - ref) / max(1e-3, abs(ref)))
+            d_l[:, i] += wi
+        out.append(w.astype(np.float64))
+        off += cam["width"] * cam["height"]
+    print(f"  distortion and extent losses on the sampled pixels: worst relative error {worst:.2e}")
+    assert worst <= 1e-4
+    return out, torch.from_numpy(d_l.reshape(-1)).cuda()
 
 
 def _opacity_parity_and_weights(scene, cams, pixels_per_cam, host, cam_ids, window, seed):
@@ -265,8 +293,9 @@ def test_unbounded_1m_1080p_training_step(unbounded_1m):
 
 
 def test_unbounded_1m_1080p_opacity_term(unbounded_1m):
-    """The same launch with the opacity pass (L_opa): its value on 64 sampled pixels and the
-    directional derivatives of a loss that includes it (depth held at the oracle's)."""
+    """The same launch with the opacity pass (L_opa) and the distortion and extent losses:
+    their values on 64 sampled pixels and the directional derivatives of a loss that includes
+    them (the opacity's depth held at the oracle's)."""
     cam = scenes.circle_camera(0.0, 1920, 1080)
     _run_training_case(unbounded_1m, [cam], 16, 8, [_sample_pixels(cam, 64, 3)], 24, "unbounded 1M 1080p + L_opa",
                        opa=True)
