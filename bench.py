@@ -84,7 +84,7 @@ def parse():
                     help="skip the comparison against one query launch per view")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-opacity-term", action="store_true",
-                    help="skip the training step with the opacity-at-depth term (L_opa)")
+                    help="skip the training step with the distortion, extent and opacity-at-depth terms")
     ap.add_argument("--no-levelset", action="store_true",
                     help="skip the level-set query and the binary search")
     ap.add_argument("--no-multiview", action="store_true",
@@ -258,13 +258,19 @@ def levelset_search(qg, pts, qcams, tile, t_exact, stream, steps=8):
 
 
 def opacity_term_step(g, C, opts, rast, out, grads, target, d_acc, d_depth, d_normal, stream, steps):
-    """The headline step plus the paper's opacity supervision: the second pass that evaluates
-    the opacity field at each pixel's rendered depth and the backward with its gradient
-    (upstream 2 lambda (O_N - 0.5) / P, lambda = 0.04 as in the paper's loss weights)."""
+    """The headline step plus the paper's rasteriser-side training terms: the distortion and
+    extent losses computed in the forward, the second pass that evaluates the opacity field at
+    each pixel's rendered depth, and the backward with all their gradients (upstream 2 lambda
+    (O_N - 0.5) / P with lambda = 0.04, and lambda_ext = 0.1 and a distortion weight of 1000 /
+    P, the order of magnitude GOF uses)."""
     import torch
     from paper_2506_19139_amd import sof
     timer = sof.KernelTimer()
     t_opa, t_step = [], []
+    P = C.n_pixels
+    out["losses"] = torch.empty(sof.LOSS_CHANNELS * P, device=out["rgb"].device)
+    d_losses = torch.cat([torch.full((P,), 1000.0 / P, device=out["rgb"].device),
+                          torch.full((P,), 0.1 / P, device=out["rgb"].device)])
 
     def step(record):
         a = [torch.cuda.Event(enable_timing=True) for _ in range(4)] if record else None
@@ -272,13 +278,13 @@ def opacity_term_step(g, C, opts, rast, out, grads, target, d_acc, d_depth, d_no
         sof.project(g, C, opts, rast.proj)
         sof.bin_sort(g.n, C, opts, rast.proj, rast.bins)
         sof.render_fwd(g.n, C, opts, rast.proj, rast.bins, out["rgb"], out["acc"], out["depth"], out["normal"],
-                       out["aux"])
+                       out["aux"], out["losses"])
         if record: a[1].record(stream)
         opa = rast.opacity(g, out)
         if record: a[2].record(stream)
         d_rgb = torch.sign(out["rgb"] - target) * (1.0 / out["rgb"].numel())
         d_opa = (opa - 0.5) * (2.0 * 0.04 / opa.numel())
-        rast.backward(g, out, d_rgb, d_acc, d_depth, d_normal, grads_out=grads, d_opa=d_opa)
+        rast.backward(g, out, d_rgb, d_acc, d_depth, d_normal, grads_out=grads, d_opa=d_opa, d_losses=d_losses)
         if record:
             a[3].record(stream)
             t_opa.append((a[1], a[2]))
@@ -292,9 +298,11 @@ def opacity_term_step(g, C, opts, rast, out, grads, target, d_acc, d_depth, d_no
             step(True)
     torch.cuda.synchronize()
     ms = lambda v: float(np.mean([x.elapsed_time(y) for x, y in v]))
-    return {"opacity_pass_ms": round(ms(t_opa), 4), "k_render_bwd_ms": round(float(np.mean(timer.ms("render_bwd"))), 4),
+    return {"k_render_fwd_ms": round(float(np.mean(timer.ms("render_fwd"))), 4),
+            "opacity_pass_ms": round(ms(t_opa), 4), "k_render_bwd_ms": round(float(np.mean(timer.ms("render_bwd"))), 4),
             "step_ms": round(ms(t_step), 4),
-            "workload": "headline step + opacity at the rendered depth (second pass) and its gradient"}
+            "workload": "headline step + distortion and extent losses + opacity at the rendered depth, "
+                        "with all their gradients"}
 
 
 # --------------------------------------------------------------------------- GPU
