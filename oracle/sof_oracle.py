@@ -26,6 +26,8 @@ paper's definitions:
   Supervision"
 * distortion and extent losses                       -- Sec. 3.3 "Distortion Loss", "Extent
   Loss"; App. C.1, C.2
+* 3D filter: opacity and covariance adjustment       -- App. "Dead Gaussians" (o_hat =
+  o sqrt(|Sigma| / |Sigma + s I|))
 
 Readings of passages the paper leaves open (all listed in the design notes):
   R1  A, B, C are written with Sigma^{-1} directly (A = d^T S^-1 d, B = 2 d^T S^-1 (o-mu),
@@ -59,6 +61,9 @@ Readings of passages the paper leaves open (all listed in the design notes):
   R18 distortion and extent losses: NDC(t) = f (t - n) / ((f - n) t) with n = 0.2, f = 100 on
       the ray distance (its derivative is the f n / ((f - n) t^2) of App. C.2); the depth of a
       Gaussian is its t*; sums run over the Gaussians the pixel blends with w = alpha T.
+  R19 3D filter size (the paper takes it from Mip-Splatting): s_i = (k z_i / f)^2 for the
+      camera that samples the centre most finely (largest f / z among cameras whose image
+      contains the projected centre beyond the near plane), k = 0.2; no camera: s_i = 0.
 """
 
 from __future__ import annotations
@@ -710,3 +715,30 @@ def bisect_level_set(scene: Scene, cams, a, b, steps=8):
         b = np.where(ins[:, None], b, mid)
         decisions.append(ins)
     return 0.5 * (a + b), np.array(decisions).reshape(steps, len(a))
+
+
+# ----------------------------------------------------------------------------------------
+# 3D filter (App. "Dead Gaussians"; filter size per R19)
+# ----------------------------------------------------------------------------------------
+
+def filter3d_variance(scene: Scene, cams, k=0.2):
+    """s_i = (k / nu_i)^2, nu_i = max f_x / z over cameras that see the centre (R19)."""
+    s = np.zeros(scene.n)
+    for i in range(scene.n):
+        best = 0.0
+        for cam in cams:
+            if point_view_valid(cam, scene.means[i]):
+                z = (cam.R @ scene.means[i] + cam.t)[2]
+                best = max(best, cam.fx / z)
+        s[i] = (k / best) ** 2 if best > 0.0 else 0.0
+    return s
+
+
+def filter3d(scene: Scene, var):
+    """Sigma + s I keeps the rotation and adds s to every squared scale; the opacity is
+    scaled by sqrt(|Sigma| / |Sigma + s I|).  Returns (scales, opacities)."""
+    s2 = scene.scales ** 2
+    new_s2 = s2 + var[:, None]
+    det_ratio = np.linalg.det(scene.covariances()) / np.linalg.det(
+        scene.covariances() + var[:, None, None] * np.eye(3)[None])
+    return np.sqrt(new_s2), scene.opac * np.sqrt(det_ratio)

@@ -607,3 +607,30 @@ def test_distortion_of_two_gaussians_and_its_prefix_form():
             assert dist == pytest.approx(2 * pref, rel=1e-9, abs=1e-15)
             n += 1
     assert n >= 50
+
+
+# --------------------------------------------------------------------------- 3D filter
+
+def test_filter3d_closed_forms():
+    """|Sigma| / |Sigma + s I| = prod s_j^2 / prod (s_j^2 + s) for any rotation (eigenvalues
+    shift by s), so o_hat = o prod s_j / sqrt(s_j^2 + s); an isotropic Gaussian gives
+    o (sigma^2 / (sigma^2 + s))^(3/2).  The filter size uses the camera with the largest
+    f / z that sees the centre."""
+    rng = np.random.default_rng(0)
+    q = rng.normal(size=(5, 4))
+    sc = O.Scene(rng.normal(size=(5, 3)), np.exp(rng.normal(-2, 0.5, (5, 3))), q, rng.uniform(0.1, 1.0, 5),
+                 np.zeros((5, 1, 3)), 0)
+    var = rng.uniform(1e-4, 1e-2, 5)
+    sc_f, o_f = O.filter3d(sc, var)
+    expect = sc.opac * np.prod(sc.scales / np.sqrt(sc.scales ** 2 + var[:, None]), axis=1)
+    assert np.allclose(o_f, expect, rtol=1e-10)
+    assert np.allclose(sc_f, np.sqrt(sc.scales ** 2 + var[:, None]), rtol=1e-15)
+    iso = one_gaussian((0, 0, 3.0), 0.1, 0.7)
+    _, o_iso = O.filter3d(iso, np.array([0.003]))
+    assert o_iso[0] == pytest.approx(0.7 * (0.01 / 0.013) ** 1.5, rel=1e-12)
+    near = O.Camera(np.eye(3), np.zeros(3), 100.0, 100.0, 32.0, 32.0, 64, 64)      # sees (0,0,3) at z 3
+    far = O.Camera(np.eye(3), np.array([0, 0, 5.0]), 100.0, 100.0, 32.0, 32.0, 64, 64)  # at z 8
+    away = O.Camera(np.diag([-1.0, 1.0, -1.0]), np.zeros(3), 500.0, 500.0, 32.0, 32.0, 64, 64)  # behind
+    var_iso = O.filter3d_variance(iso, [far, near, away], k=0.2)
+    assert var_iso[0] == pytest.approx((0.2 * 3.0 / 100.0) ** 2, rel=1e-12)
+    assert O.filter3d_variance(iso, [away])[0] == 0.0
