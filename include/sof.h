@@ -17,6 +17,7 @@
  *   sof_render_opacity opacity field at each pixel's rendered depth (Sec. 3.3, the L_opa term).
  *   sof_render_bwd     adjoint of render + project: replays each pixel's order front to back,
  *                      recomputing transmittance, and writes gradients for mu, s, q, o, f.
+ *   sof_filter3d       the 3D filter's opacity and covariance adjustment (App. "Dead Gaussians").
  *   sof_opacity_query  opacity field O(x) = min over views of O_N(x) (Eq. (12)-(13)) at
  *                      arbitrary points, with tile scheduling of points (Sec. 3.4, Eq. (14))
  *                      and z_min early stopping (Eq. (15)); all views in one persistent launch.
@@ -248,6 +249,28 @@ int sof_opacity_query(const sof_gaussians* g, const sof_camera* h_cams, const so
                       int32_t n_cams, const sof_options* opts, const float* points, int64_t n_points,
                       int64_t pv_capacity, float* opacity, void* proj, size_t proj_bytes, void* bins,
                       size_t bins_bytes, void* sched, size_t sched_bytes, hipStream_t stream);
+
+/*
+ * sof_filter3d -- the 3D filter of App. "Dead Gaussians": Sigma + s I for a per-Gaussian
+ * filter size s, and o_hat = o sqrt(|Sigma| / |Sigma + s I|).  s follows the filter the paper
+ * adopts: s = (k z / f_x)^2 for the camera with the largest f_x / z whose image contains the
+ * projected centre beyond near_plane (k = 0.2 there), s = 0 when no camera does.  Writes
+ * var [n] = s, scales_out [n,3] = sqrt(scales^2 + s) (the rotation is unchanged) and
+ * opacities_out [n] = o prod_j scales_j / scales_out_j.  Only means, scales and opacities
+ * of g are read.  n_cams may be 0 (no filtering).
+ */
+int sof_filter3d(const sof_gaussians* g, const sof_camera* h_cams, const sof_camera* d_cams, int32_t n_cams,
+                 float near_plane, float k, float* var, float* scales_out, float* opacities_out,
+                 hipStream_t stream);
+
+/*
+ * sof_filter3d_bwd -- adjoint of sof_filter3d with var held constant: from the upstream
+ * gradients of scales_out and opacities_out (NULL = zero) writes (overwrites) d_scales [n,3]
+ * and d_opacities [n] with respect to the unfiltered scales and opacities.
+ */
+int sof_filter3d_bwd(const sof_gaussians* g, const float* var, const float* d_scales_out,
+                     const float* d_opacities_out, float* d_scales, float* d_opacities,
+                     hipStream_t stream);
 
 /*
  * Instrumentation, not part of the method: per-kernel timing for benchmarks.  `events`

@@ -182,6 +182,25 @@ int sof_render_fwd(int64_t n, const sof_camera* h_cams, const sof_camera* d_cams
   return hip_status(e);
 }
 
+int sof_filter3d(const sof_gaussians* g, const sof_camera* h_cams, const sof_camera* d_cams, int32_t n_cams,
+                 float near_plane, float k, float* var, float* scales_out, float* opacities_out, hipStream_t stream) {
+  if (!g || g->n < 0 || g->n >= (int64_t(1) << 31) || n_cams < 0 || !(near_plane > 0.f) || !(k >= 0.f))
+    return SOF_E_ARG;
+  if (g->n > 0 && (!g->means || !g->scales || !g->opacities || !var || !scales_out || !opacities_out))
+    return SOF_E_ARG;
+  if (n_cams > 0 && (!h_cams || !d_cams)) return SOF_E_ARG;
+  return hip_status(launch_filter3d(g->means, g->scales, g->opacities, g->n, d_cams, n_cams, near_plane, k, var,
+                                    scales_out, opacities_out, stream));
+}
+
+int sof_filter3d_bwd(const sof_gaussians* g, const float* var, const float* d_scales_out,
+                     const float* d_opacities_out, float* d_scales, float* d_opacities, hipStream_t stream) {
+  if (!g || g->n < 0 || g->n >= (int64_t(1) << 31)) return SOF_E_ARG;
+  if (g->n > 0 && (!g->scales || !g->opacities || !var || !d_scales || !d_opacities)) return SOF_E_ARG;
+  return hip_status(launch_filter3d_bwd(g->scales, g->opacities, var, g->n, d_scales_out, d_opacities_out, d_scales,
+                                        d_opacities, stream));
+}
+
 int sof_render_opacity(int64_t n, const sof_camera* h_cams, const sof_camera* d_cams, int32_t n_cams,
                        const sof_options* opts, const void* proj, size_t proj_bytes, const void* bins,
                        size_t bins_bytes, const float* depth, const float* aux, float* opacity, hipStream_t stream) {

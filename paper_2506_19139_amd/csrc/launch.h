@@ -102,6 +102,13 @@ struct ProjectBwdArgs {
 };
 hipError_t launch_project_bwd(const ProjectBwdArgs& a, hipStream_t s);
 
+hipError_t launch_filter3d(const float* means, const float* scales, const float* opac, int64_t n,
+                           const sof_camera* cams, int n_cams, float near_plane, float k, float* var,
+                           float* scales_out, float* opac_out, hipStream_t s);
+hipError_t launch_filter3d_bwd(const float* scales, const float* opac, const float* var, int64_t n,
+                               const float* d_scales_out, const float* d_opac_out, float* d_scales, float* d_opac,
+                               hipStream_t s);
+
 // Optional timing events recorded around single kernels (see sof_set_timing_events).
 enum TimedKernel { kTimeRenderFwd = 0, kTimeRenderBwd = 1, kTimeQuery = 2, kTimedKernels = 3 };
 void timing_mark(TimedKernel k, int end, hipStream_t s);

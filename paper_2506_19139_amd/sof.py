@@ -75,6 +75,8 @@ _SIGS = {
                                                 ctypes.c_int64, _SZ, _SZ, _SZ]),
     "sof_opacity_query": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, _P, _P, ctypes.c_int64, ctypes.c_int64,
                                          _P, _P, ctypes.c_size_t, _P, ctypes.c_size_t, _P, ctypes.c_size_t, _P]),
+    "sof_filter3d": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, ctypes.c_float, ctypes.c_float, _P, _P, _P, _P]),
+    "sof_filter3d_bwd": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P]),
     "sof_set_timing_events": (ctypes.c_int, [_P]),
     "sof_bisect_step": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int64, _P]),
     "sof_strerror": (ctypes.c_char_p, [ctypes.c_int]),
@@ -245,6 +247,28 @@ def render_bwd(g: Gaussians, cams: Cameras, opts: Options, proj, bins, rgb, norm
                                 grads.numel() if grads is not None else 0,
                                 _ptr(d_means), _ptr(d_scales), _ptr(d_quats), _ptr(d_opac), _ptr(d_sh), _stream()),
            "sof_render_bwd")
+
+
+def filter3d(g: Gaussians, cams: Cameras, k=0.2, near_plane=0.2):
+    """3D filter: (filtered Gaussians, per-Gaussian filter size s).  The filtered set shares
+    means, rotations and colours with g."""
+    var = torch.empty_like(g.opac)
+    scales, opac = torch.empty_like(g.scales), torch.empty_like(g.opac)
+    gs = g.c_struct()
+    n_cams = len(cams) if cams is not None else 0
+    _check(lib().sof_filter3d(ctypes.byref(gs), cams.hp() if n_cams else None, cams.dp() if n_cams else None, n_cams,
+                              float(near_plane), float(k), _ptr(var), _ptr(scales), _ptr(opac), _stream()),
+           "sof_filter3d")
+    return Gaussians(g.means, scales, g.quats, opac, g.sh, g.sh_degree), var
+
+
+def filter3d_bwd(g: Gaussians, var, d_scales_out, d_opac_out):
+    """Gradients with respect to g's scales and opacities from those of the filtered set."""
+    d_scales, d_opac = torch.empty_like(g.scales), torch.empty_like(g.opac)
+    gs = g.c_struct()
+    _check(lib().sof_filter3d_bwd(ctypes.byref(gs), _ptr(var), _ptr(d_scales_out), _ptr(d_opac_out), _ptr(d_scales),
+                                  _ptr(d_opac), _stream()), "sof_filter3d_bwd")
+    return d_scales, d_opac
 
 
 def read_status(buf: torch.Tensor):

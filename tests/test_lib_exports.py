@@ -14,7 +14,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def declared_functions():
     txt = open(os.path.join(ROOT, "include", "sof.h")).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"\b(sof_[a-z_]+)\s*\(", txt)))
+    return sorted(set(re.findall(r"\b(sof_[a-z0-9_]+)\s*\(", txt)))
 
 
 def test_header_declares_the_five_hot_path_calls():
