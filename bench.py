@@ -469,6 +469,17 @@ def main():
         if not args.no_per_view:
             log("query, one launch per view")
             result["query"]["per_view_launches"] = per_view_query(qg, pts, qcams, args.query_tile, o, tq, stream)
+        log("3D filter")
+        sof.filter3d(qg, qcams)
+        torch.cuda.synchronize()
+        f0, f1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        f0.record(stream)
+        gf, fvar = sof.filter3d(qg, qcams)
+        f1.record(stream)
+        torch.cuda.synchronize()
+        result["filter3d"] = {"workload": f"{qg.n} Gaussians, {len(qcams)} cameras", "ms": round(f0.elapsed_time(f1), 3),
+                              "below_1_255_after_filter": round(float((gf.opac < 1.0 / 255).float().mean()), 4)}
+        del gf, fvar
         if not args.no_levelset:
             log("level-set query and binary search")
             result["levelset"] = levelset_search(qg, pts, qcams, args.query_tile, tq, stream)
