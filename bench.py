@@ -45,8 +45,8 @@ KERNEL_SOURCES = {
     "k_render_bwd": ("render_bwd.hip", "render_common.h", "sof_internal.h", "launch.h"),
 }
 COUNTERS = {                        # kernel -> sources hash, counter KiB per dispatch
-    "k_render_bwd": {"src": "f4f6c558311f2896", "fetch_kib": 663503.0, "write_kib": 211863.2},
-    "k_render_fwd": {"src": "be6461e92c092203", "fetch_kib": 332055.3, "write_kib": 124423.2},
+    "k_render_bwd": {"src": "101a0b8737eed8c7", "fetch_kib": 662749.1, "write_kib": 211866.0},
+    "k_render_fwd": {"src": "c963f8532dcad0f9", "fetch_kib": 332244.3, "write_kib": 124418.9},
 }
 COUNTER_SCALE = {"fetch": 0.50002, "write": 1.0}    # counter KiB per KiB moved by the 1 GiB copy
 
