@@ -51,3 +51,18 @@ def test_host_argument_checks():
     assert L.sof_workspace_size(-1, hp, 1, ctypes.byref(o), None, None, None) == sof.SOF_E_ARG
     cam[0].width = 0
     assert L.sof_workspace_size(100, hp, 1, ctypes.byref(o), None, None, None) == sof.SOF_E_ARG
+    cam[0].width = 64
+    # binary-search step: empty input is a no-op, missing arrays or a negative size are rejected
+    assert L.sof_bisect_step(None, None, None, None, 0, None) == sof.SOF_OK
+    assert L.sof_bisect_step(None, None, None, None, 5, None) == sof.SOF_E_ARG
+    assert L.sof_bisect_step(None, None, None, None, -1, None) == sof.SOF_E_ARG
+    # 3D filter: no Gaussians is a no-op; a missing Gaussian set or a bad near plane is rejected
+    gs = sof.CGaussians(0, 0, 0, None, None, None, None, None)
+    assert L.sof_filter3d(ctypes.byref(gs), hp, None, 1, 0.2, 0.2, None, None, None, None) == sof.SOF_E_ARG
+    assert L.sof_filter3d(ctypes.byref(gs), None, None, 0, 0.2, 0.2, None, None, None, None) == sof.SOF_OK
+    assert L.sof_filter3d(None, None, None, 0, 0.2, 0.2, None, None, None, None) == sof.SOF_E_ARG
+    assert L.sof_filter3d(ctypes.byref(gs), None, None, 0, 0.0, 0.2, None, None, None, None) == sof.SOF_E_ARG
+    assert L.sof_filter3d_bwd(ctypes.byref(gs), None, None, None, None, None, None) == sof.SOF_OK
+    # opacity pass: the forward's depth and aux are required
+    assert L.sof_render_opacity(0, hp, hp, 1, ctypes.byref(o), None, 0, None, 0, None, None, None,
+                                None) == sof.SOF_E_ARG
