@@ -324,16 +324,30 @@ __global__ __launch_bounds__(TS * TS) void k_render_bwd(RenderBwdArgs A) {
         dop += dl * qal / r3.y;
       }
     }
-    const float sA = ds / Am, hA = 0.5f * sA, dq2 = 2.f * dq;
-    gv[0] = dq2 * Prx + sA * Pdx;
-    gv[1] = dq2 * Pry + sA * Pdy;
-    gv[2] = dq2 * Prz + sA * Pdz;
-    gv[3] = dq * rxv * rxv + hA * 2.f * dvx * rxv + dA * dvx * dvx;
-    gv[4] = dq * rxv * ryv + hA * (dvx * ryv + rxv * dvy) + dA * dvx * dvy;
-    gv[5] = dq * rxv * rzv + hA * (dvx * rzv + rxv) + dA * dvx;
-    gv[6] = dq * ryv * ryv + hA * 2.f * dvy * ryv + dA * dvy * dvy;
-    gv[7] = dq * ryv * rzv + hA * (dvy * rzv + ryv) + dA * dvy;
-    gv[8] = dq * rzv * rzv + hA * 2.f * rzv + dA;
+    const float dq2 = 2.f * dq;
+    gv[0] = dq2 * Prx;
+    gv[1] = dq2 * Pry;
+    gv[2] = dq2 * Prz;
+    gv[3] = dq * rxv * rxv;
+    gv[4] = dq * rxv * ryv;
+    gv[5] = dq * rxv * rzv;
+    gv[6] = dq * ryv * ryv;
+    gv[7] = dq * ryv * rzv;
+    gv[8] = dq * rzv * rzv;
+    // terms of the peak depth s* and of A = d^T P d: only the crossing Gaussian (exact depth)
+    // and the optional losses have them, so the wave takes this branch rarely otherwise
+    if (__any(ds != 0.f || dA != 0.f)) {
+      const float sA = ds / Am, hA = 0.5f * sA;
+      gv[0] = fmaf(sA, Pdx, gv[0]);
+      gv[1] = fmaf(sA, Pdy, gv[1]);
+      gv[2] = fmaf(sA, Pdz, gv[2]);
+      gv[3] += hA * 2.f * dvx * rxv + dA * dvx * dvx;
+      gv[4] += hA * (dvx * ryv + rxv * dvy) + dA * dvx * dvy;
+      gv[5] += hA * (dvx * rzv + rxv) + dA * dvx;
+      gv[6] += hA * 2.f * dvy * ryv + dA * dvy * dvy;
+      gv[7] += hA * (dvy * rzv + ryv) + dA * dvy;
+      gv[8] += hA * 2.f * rzv + dA;
+    }
     gv[9] = dop;
     gv[10] = gr * w; gv[11] = gg * w; gv[12] = gb * w;
     gv[13] = gnx * w; gv[14] = gny * w; gv[15] = gnz * w;
