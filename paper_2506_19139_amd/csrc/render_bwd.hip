@@ -75,8 +75,7 @@ __global__ __launch_bounds__(TS * TS) void k_render_bwd(RenderBwdArgs A) {
                                                  // of neighbouring slots fall in distinct banks
   constexpr int kGroupReduce = 4;                // lanes sharing an instance: reduce first
   __shared__ float gsl[kSlotStride * NS];
-  __shared__ uint32_t ring_e[NS];                // emission index of each resident list slot
-  __shared__ int32_t ring_g[NS];                 // and its Gaussian
+  __shared__ uint2 ring[NS];                     // (emission index, Gaussian) of each resident list slot
   const RenderFwdArgs& a = A.f;
   const int tile = blockIdx.x;
   const int c = find_cam(a.cam_info, a.n_cams, tile);
@@ -203,8 +202,9 @@ __global__ __launch_bounds__(TS * TS) void k_render_bwd(RenderBwdArgs A) {
   // Gaussian of list slot `pos`: from the LDS ring while its batch is resident
   auto slot_gaussian = [&](uint32_t pos, int cur_b, uint32_t& e) -> int32_t {
     if ((int)pos >= (cur_b - 1) * B) {
-      e = ring_e[pos % NS];
-      return ring_g[pos % NS];
+      const uint2 r = ring[pos % NS];
+      e = r.x;
+      return (int32_t)r.y;
     }
     e = A.f.vals[rg.x + (int)pos];
     return A.f.gid[e];
@@ -219,7 +219,7 @@ __global__ __launch_bounds__(TS * TS) void k_render_bwd(RenderBwdArgs A) {
     const float Tj = p.T;
     const float w = al * Tj;
     const float om = 1.f - al;
-    const float iom = 1.f / om;
+    const float iom = __builtin_amdgcn_rcpf(om);
     p.cr = fmaf(w, col.x, p.cr); p.cg = fmaf(w, col.y, p.cg); p.cb = fmaf(w, col.z, p.cb);
     p.nx = fmaf(w, nrm.x, p.nx); p.ny = fmaf(w, nrm.y, p.ny); p.nz = fmaf(w, nrm.z, p.nz);
     float dal = gr * (col.x * Tj - (fr - p.cr) * iom) + gg * (col.y * Tj - (fg - p.cg) * iom) +
@@ -232,7 +232,7 @@ __global__ __launch_bounds__(TS * TS) void k_render_bwd(RenderBwdArgs A) {
     if (!p.crossed && !is_k) dal -= cT * Tk * iom;
     const bool clamped = al >= kAlphaMax;                 // alpha = min(0.99, o G*)
     float dq = clamped ? 0.f : -0.5f * al * dal;          // dalpha/dq* = -alpha/2
-    float dop = clamped ? 0.f : dal * (al / o);           // dalpha/do = G*
+    float dop = clamped ? 0.f : dal * al * __builtin_amdgcn_rcpf(o);   // dalpha/do = G*
     uint32_t tag = pos;
     if (is_k) {
       k_ds = gd * dn;
@@ -258,7 +258,7 @@ __global__ __launch_bounds__(TS * TS) void k_render_bwd(RenderBwdArgs A) {
   // One emitted Gaussian: gradients with respect to mu_c and P_c and the colour and
   // normal partials of this pixel.
   auto heavy = [&](uint32_t tag, float dq, float dop, float w, float* gv) {
-    const bool crossing = (tag & kCrossBit) != 0u;
+    const bool crossing = has && (tag & kCrossBit) != 0u;
     const int64_t vg = cam_base + qg;
     const float4 r0 = a.geom[4 * vg], r1 = a.geom[4 * vg + 1], r2 = a.geom[4 * vg + 2], r3 = a.geom[4 * vg + 3];
     const float4 p0 = A.bwdr[2 * vg], p1 = A.bwdr[2 * vg + 1];
@@ -266,7 +266,7 @@ __global__ __launch_bounds__(TS * TS) void k_render_bwd(RenderBwdArgs A) {
     const float dx = dd.x, dy = dd.y;
     const Quad q = quad_terms(r1.x, r1.y, r1.z, r1.w, r2.x, r2.y, r2.z, r2.w, dx, dy);
     const float mz = r3.x, aa = r3.w;
-    const float iden = 1.f / q.den;
+    const float iden = __builtin_amdgcn_rcpf(q.den);
     const float sstar = mz * (1.f + q.b) * iden;
     float ds = crossing ? k_ds : 0.f;
     float dA = crossing ? k_dA : 0.f;
@@ -337,7 +337,7 @@ __global__ __launch_bounds__(TS * TS) void k_render_bwd(RenderBwdArgs A) {
     // terms of the peak depth s* and of A = d^T P d: only the crossing Gaussian (exact depth)
     // and the optional losses have them, so the wave takes this branch rarely otherwise
     if (__any(ds != 0.f || dA != 0.f)) {
-      const float sA = ds / Am, hA = 0.5f * sA;
+      const float sA = ds * __builtin_amdgcn_rcpf(Am), hA = 0.5f * sA;
       gv[0] = fmaf(sA, Pdx, gv[0]);
       gv[1] = fmaf(sA, Pdy, gv[1]);
       gv[2] = fmaf(sA, Pdz, gv[2]);
@@ -389,9 +389,15 @@ __global__ __launch_bounds__(TS * TS) void k_render_bwd(RenderBwdArgs A) {
     float gv[kGradFields];
     const uint32_t pos = has ? (qtag & ~kCrossBit) : 0xFFFFFFFFu;
     const uint32_t e = qe;
+    if constexpr (EXT) {
 #pragma unroll
-    for (int f = 0; f < kGradFields; ++f) gv[f] = 0.f;
-    if (has) heavy(qtag, qdq, qdo, qw, gv);
+      for (int f = 0; f < kGradFields; ++f) gv[f] = 0.f;
+      if (has) heavy(qtag, qdq, qdo, qw, gv);          // the loss prefixes advance on emission only
+    } else {
+      // lanes without a pending entry compute on their last (or the first) Gaussian; every
+      // use of gv below is masked by has, so their values are never read
+      heavy(qtag, qdq, qdo, qw, gv);
+    }
     const int resident_from = (cur_b - 1) * B;
     const bool resident = has && (int)pos >= resident_from;
     if (has && !resident) {
@@ -458,8 +464,7 @@ __global__ __launch_bounds__(TS * TS) void k_render_bwd(RenderBwdArgs A) {
       const int32_t g = A.f.gid[e];
       stage_entry(a.geom, a.rect, cam_base + g, x0, y0, (uint32_t)(i - rg.x), &stage[threadIdx.x],
                   &srect[threadIdx.x]);
-      ring_e[(i - rg.x) % NS] = e;
-      ring_g[(i - rg.x) % NS] = g;
+      ring[(i - rg.x) % NS] = make_uint2(e, (uint32_t)g);
     }
     // The flushed slots and any later global atomics on them (entries emitted after their
     // batch left the ring) come from this workgroup only: waiting until this lane's stores
