@@ -185,19 +185,16 @@ __global__ __launch_bounds__(TS * TS) void k_render_bwd(RenderBwdArgs A) {
   Window<W> win;
   win.init();
 
-  // Emission, in the forward's order: transmittance, prefix sums and dL/dalpha need only the
-  // Gaussian's colour, normal and opacity; they leave (tag, dq, dop, w) in the lane's
-  // pending slot.  The chain rule to (mu_c, P_c) and the accumulation then run once per list
-  // step for all lanes that emitted in it, so lanes holding the same Gaussian can be summed
-  // across the wave before touching LDS.
-  constexpr uint32_t kCrossBit = 0x80000000u;
+  // Emission, in the forward's order.  The window holds (key, list slot) only: when an entry
+  // leaves it the lane marks the slot pending, and once per list step every lane with a
+  // pending slot gathers the Gaussian, recomputes its alpha (bit-identical to the candidate
+  // test: same pixel offset, quadric terms, reciprocal and exp2), advances the transmittance
+  // and prefix sums and forms all partials.  The partials are then added wave-cooperatively,
+  // so lanes holding the same Gaussian can be summed across the wave before touching LDS.
   bool has = false;
-  uint32_t qtag = 0u;
-  float qdq = 0.f, qdo = 0.f, qw = 0.f;
-  uint32_t qe = 0u;
-  int32_t qg = 0;
-  float qal = 0.f, qT = 0.f;
-  float k_ds = 0.f, k_dA = 0.f;
+  uint32_t qpos = 0u;            // pending list slot
+  uint32_t qe = 0u;              // its instance (emission index)
+  int32_t qg = 0;                // and Gaussian (stale on lanes without a pending slot)
 
   // Gaussian of list slot `pos`: from the LDS ring while its batch is resident
   auto slot_gaussian = [&](uint32_t pos, int cur_b, uint32_t& e) -> int32_t {
@@ -210,66 +207,59 @@ __global__ __launch_bounds__(TS * TS) void k_render_bwd(RenderBwdArgs A) {
     return A.f.gid[e];
   };
 
-  auto emit = [&](float al, uint32_t pos, int cur_b) {
-    uint32_t e;
-    const int32_t g = slot_gaussian(pos, cur_b, e);
-    const int64_t vg = cam_base + g;
+  // One emitted Gaussian: blend state, dL/dalpha, and the gradients with respect to mu_c,
+  // P_c, the opacity, the colour and the normal.  `live` is false on lanes that compute on a
+  // stale Gaussian only to keep the wave's control flow uniform: their state is left as is.
+  auto adjoint = [&](bool live, float* gv) {
+    const int64_t vg = cam_base + qg;
+    const float4 r0 = a.geom[4 * vg], r1 = a.geom[4 * vg + 1], r2 = a.geom[4 * vg + 2], r3 = a.geom[4 * vg + 3];
+    const float4 p0 = A.bwdr[2 * vg], p1 = A.bwdr[2 * vg + 1];
     const float4 col = a.app[2 * vg], nrm = a.app[2 * vg + 1];
-    const float o = col.w;
+    const float2 dd = pixel_offset(r0, px, py);
+    const float dx = dd.x, dy = dd.y;
+    const Quad q = quad_terms(r1.x, r1.y, r1.z, r1.w, r2.x, r2.y, r2.z, r2.w, dx, dy);
+    const float iden = __builtin_amdgcn_rcpf(q.den);
+    const float xs = fmaxf(q.num * iden, 0.f);
+    const float Gs = __builtin_amdgcn_exp2f(-xs);
+    const float o = r3.y;
+    const float al = fminf(kAlphaMax, o * Gs);
+
+    // ---- blend state and dL/dalpha
     const float Tj = p.T;
     const float w = al * Tj;
     const float om = 1.f - al;
     const float iom = __builtin_amdgcn_rcpf(om);
-    p.cr = fmaf(w, col.x, p.cr); p.cg = fmaf(w, col.y, p.cg); p.cb = fmaf(w, col.z, p.cb);
-    p.nx = fmaf(w, nrm.x, p.nx); p.ny = fmaf(w, nrm.y, p.ny); p.nz = fmaf(w, nrm.z, p.nz);
-    float dal = gr * (col.x * Tj - (fr - p.cr) * iom) + gg * (col.y * Tj - (fg - p.cg) * iom) +
-                gb * (col.z * Tj - (fb - p.cb) * iom);
-    dal += gnx * (nrm.x * Tj - (fnx - p.nx) * iom) + gny * (nrm.y * Tj - (fny - p.ny) * iom) +
-           gnz * (nrm.z * Tj - (fnz - p.nz) * iom);
+    const float cr = fmaf(w, col.x, p.cr), cg = fmaf(w, col.y, p.cg), cb = fmaf(w, col.z, p.cb);
+    const float nx = fmaf(w, nrm.x, p.nx), ny = fmaf(w, nrm.y, p.ny), nz = fmaf(w, nrm.z, p.nz);
+    float dal = gr * (col.x * Tj - (fr - cr) * iom) + gg * (col.y * Tj - (fg - cg) * iom) +
+                gb * (col.z * Tj - (fb - cb) * iom);
+    dal += gnx * (nrm.x * Tj - (fnx - nx) * iom) + gny * (nrm.y * Tj - (fny - ny) * iom) +
+           gnz * (nrm.z * Tj - (fnz - nz) * iom);
     dal += ga * T_end * iom;
     const float testT = Tj * om;
-    const bool is_k = !p.crossed && testT <= 0.5f;
+    const bool is_k = live && !p.crossed && testT <= 0.5f;
     if (!p.crossed && !is_k) dal -= cT * Tk * iom;
     const bool clamped = al >= kAlphaMax;                 // alpha = min(0.99, o G*)
     float dq = clamped ? 0.f : -0.5f * al * dal;          // dalpha/dq* = -alpha/2
-    float dop = clamped ? 0.f : dal * al * __builtin_amdgcn_rcpf(o);   // dalpha/do = G*
-    uint32_t tag = pos;
+    float dop = clamped ? 0.f : dal * Gs;                 // dalpha/do = G*
+    float ds = 0.f, dA = 0.f;
     if (is_k) {
-      k_ds = gd * dn;
-      k_dA = dA_k;
+      ds = gd * dn;
+      dA = dA_k;
       dq += dq_k;
       dop += do_k;
-      p.crossed = true;
-      tag |= kCrossBit;
     }
-    p.T = testT;
-    has = true;
-    qtag = tag;
-    qdq = dq;
-    qdo = dop;
-    qw = w;
-    qe = e;
-    qg = g;
-    qal = al;
-    qT = Tj;
-    if (++p.emitted >= p.n_emit) p.done = true;
-  };
+    if (live) {
+      p.cr = cr; p.cg = cg; p.cb = cb;
+      p.nx = nx; p.ny = ny; p.nz = nz;
+      p.T = testT;
+      if (is_k) p.crossed = true;
+      if (++p.emitted >= p.n_emit) p.done = true;
+    }
 
-  // One emitted Gaussian: gradients with respect to mu_c and P_c and the colour and
-  // normal partials of this pixel.
-  auto heavy = [&](uint32_t tag, float dq, float dop, float w, float* gv) {
-    const bool crossing = has && (tag & kCrossBit) != 0u;
-    const int64_t vg = cam_base + qg;
-    const float4 r0 = a.geom[4 * vg], r1 = a.geom[4 * vg + 1], r2 = a.geom[4 * vg + 2], r3 = a.geom[4 * vg + 3];
-    const float4 p0 = A.bwdr[2 * vg], p1 = A.bwdr[2 * vg + 1];
-    const float2 dd = pixel_offset(r0, px, py);
-    const float dx = dd.x, dy = dd.y;
-    const Quad q = quad_terms(r1.x, r1.y, r1.z, r1.w, r2.x, r2.y, r2.z, r2.w, dx, dy);
+    // ---- chain rule to (mu_c, P_c)
     const float mz = r3.x, aa = r3.w;
-    const float iden = __builtin_amdgcn_rcpf(q.den);
     const float sstar = mz * (1.f + q.b) * iden;
-    float ds = crossing ? k_ds : 0.f;
-    float dA = crossing ? k_dA : 0.f;
     const float dnx = dx * ifx, dny = dy * ify;
     const float dmx = p1.z, dmy = p1.w;
     const float dvx = dmx + dnx, dvy = dmy + dny;               // d = (dvx, dvy, 1)
@@ -279,9 +269,6 @@ __global__ __launch_bounds__(TS * TS) void k_render_bwd(RenderBwdArgs A) {
     const float Prx = P00 * rxv + P01 * ryv + P02 * rzv;
     const float Pry = P01 * rxv + P11 * ryv + P12 * rzv;
     const float Prz = P02 * rxv + P12 * ryv + P22 * rzv;
-    const float Pdx = P00 * dvx + P01 * dvy + P02;
-    const float Pdy = P01 * dvx + P11 * dvy + P12;
-    const float Pdz = P02 * dvx + P12 * dvy + P22;
     const float Am = aa * q.den;
     // distortion and extent losses (App. C.1, C.2), in blend order: dL/dalpha through the
     // weights (prefix sums from the running totals), plus the direct terms of d = NDC(t*)
@@ -291,37 +278,37 @@ __global__ __launch_bounds__(TS * TS) void k_render_bwd(RenderBwdArgs A) {
         const float t = dn * sstar;
         const float d = kNdcFar * (t - kNdcNear) / ((kNdcFar - kNdcNear) * t);
         const float ndcp = kKappa / (t * t);
-        const float Tn = qT * (1.f - qal);
+        const float Tn = testT;
         // L_dist = sum_ij w_i w_j (d_i - d_j)^2: dL/dw_k = 2 (A (d_k - mu)^2 + M), and the
         // suffix sum_{i>k} w_i dL/dw_i = 2 (A (M - prefix_k) + M (A - A_k))
         const float dc = d - mu;
         const float cd = 2.f * (Atot * dc * dc + Mtot);
         Mp = fmaf(w * dc, dc, Mp);
         const float Sd = 2.f * (Atot * (Mtot - Mp) + Mtot * (Atot - (1.f - Tn)));
-        float dal_x = g_dist * (cd * qT - Sd / (1.f - qal));
+        float dal_x = g_dist * (cd * Tj - Sd / (1.f - al));
         ds += g_dist * 4.f * w * Atot * dc * ndcp * dn;                   // dL/dd_k = 4 w_k A (d_k - mu)
-        const float qs = fmaxf(q.num * iden, 0.f) * (2.f * kLn2);
-        const float u = fmaxf(2.f * logf(255.f * r3.y) - qs, 1e-12f);
+        const float qs = xs * (2.f * kLn2);
+        const float u = fmaxf(2.f * logf(255.f * o) - qs, 1e-12f);
         const float e = sqrtf(u / Am) / (dn * sstar * sstar);
         Ep = fmaf(w, e, Ep);
-        dal_x += g_ext * kKappa * (e * qT - (Etot - Ep) / (1.f - qal));
+        dal_x += g_ext * kKappa * (e * Tj - (Etot - Ep) / (1.f - al));
         const float ce = g_ext * kKappa * w;
         dq -= ce * e / (2.f * u);
         dA -= ce * e / (2.f * Am);
         ds -= ce * 2.f * e / sstar;
-        dop += ce * e / (u * r3.y);
-        if (qal < kAlphaMax) {
-          dq -= 0.5f * qal * dal_x;
-          dop += dal_x * qal / r3.y;
+        dop += ce * e / (u * o);
+        if (al < kAlphaMax) {
+          dq -= 0.5f * al * dal_x;
+          dop += dal_x * al / o;
         }
       }
     }
     // opacity at the rendered depth, peak in front of x: alpha_j(x) is the blend alpha
     if constexpr (EXT) {
-      if (opa_on && sstar <= s_r && qal < kAlphaMax) {
-        const float dl = gopaP / (1.f - qal);
-        dq -= 0.5f * qal * dl;
-        dop += dl * qal / r3.y;
+      if (opa_on && sstar <= s_r && al < kAlphaMax) {
+        const float dl = gopaP / (1.f - al);
+        dq -= 0.5f * al * dl;
+        dop += dl * al / o;
       }
     }
     const float dq2 = 2.f * dq;
@@ -337,6 +324,9 @@ __global__ __launch_bounds__(TS * TS) void k_render_bwd(RenderBwdArgs A) {
     // terms of the peak depth s* and of A = d^T P d: only the crossing Gaussian (exact depth)
     // and the optional losses have them, so the wave takes this branch rarely otherwise
     if (__any(ds != 0.f || dA != 0.f)) {
+      const float Pdx = P00 * dvx + P01 * dvy + P02;
+      const float Pdy = P01 * dvx + P11 * dvy + P12;
+      const float Pdz = P02 * dvx + P12 * dvy + P22;
       const float sA = ds * __builtin_amdgcn_rcpf(Am), hA = 0.5f * sA;
       gv[0] = fmaf(sA, Pdx, gv[0]);
       gv[1] = fmaf(sA, Pdy, gv[1]);
@@ -356,8 +346,7 @@ __global__ __launch_bounds__(TS * TS) void k_render_bwd(RenderBwdArgs A) {
     if constexpr (EXT) {
       if (opa_on && sstar > s_r) {
         const float dsr = s_r - sstar;
-        const float xs = fmaxf(q.num * iden, 0.f);
-        const float araw = r3.y * exp2f(-(xs + kHalfLog2e * Am * dsr * dsr));
+        const float araw = o * exp2f(-(xs + kHalfLog2e * Am * dsr * dsr));
         const float ax = fminf(kAlphaMax, araw);
         if (ax >= kAlphaMin && s_r > near_plane && araw < kAlphaMax) {
           const float dl = gopaP / (1.f - ax);
@@ -373,13 +362,13 @@ __global__ __launch_bounds__(TS * TS) void k_render_bwd(RenderBwdArgs A) {
           gv[6] += dqx * uy * uy;
           gv[7] += dqx * uy * uz;
           gv[8] += dqx * uz * uz;
-          gv[9] += dl * ax / r3.y;
+          gv[9] += dl * ax / o;
         }
       }
     }
   };
 
-  // Every lane with a pending Gaussian computes its partials; they are then added
+  // Every lane with a pending slot computes its partials; they are then added
   // wave-cooperatively.  Lanes of one wave often hold the same instance (neighbouring
   // pixels share Gaussians), and float atomics to one LDS address serialise, so lanes are
   // grouped by instance: small groups add directly, a larger group is first summed across
@@ -387,16 +376,17 @@ __global__ __launch_bounds__(TS * TS) void k_render_bwd(RenderBwdArgs A) {
   // once.  Entries older than the two resident batches add to the global buffer.
   auto round = [&](int cur_b) {
     float gv[kGradFields];
-    const uint32_t pos = has ? (qtag & ~kCrossBit) : 0xFFFFFFFFu;
+    if (has) qg = slot_gaussian(qpos, cur_b, qe);
+    const uint32_t pos = has ? qpos : 0xFFFFFFFFu;
     const uint32_t e = qe;
     if constexpr (EXT) {
 #pragma unroll
       for (int f = 0; f < kGradFields; ++f) gv[f] = 0.f;
-      if (has) heavy(qtag, qdq, qdo, qw, gv);          // the loss prefixes advance on emission only
+      if (has) adjoint(true, gv);                        // the loss prefixes advance on emission only
     } else {
-      // lanes without a pending entry compute on their last (or the first) Gaussian; every
+      // lanes without a pending slot compute on their last (or the first) Gaussian; every
       // use of gv below is masked by has, so their values are never read
-      heavy(qtag, qdq, qdo, qw, gv);
+      adjoint(has, gv);
     }
     const int resident_from = (cur_b - 1) * B;
     const bool resident = has && (int)pos >= resident_from;
@@ -485,7 +475,11 @@ __global__ __launch_bounds__(TS * TS) void k_render_bwd(RenderBwdArgs A) {
         if (cand) {
           float ea;
           uint32_t et;
-          if (win.push(key, al, __float_as_uint(e.tag), ea, et)) emit(ea, et, cur_b);
+          // alpha is recomputed on emission, so the window carries none (its moves fold away)
+          if (win.push(key, 0.f, __float_as_uint(e.tag), ea, et)) {
+            has = true;
+            qpos = et;
+          }
         }
         if (__any(has)) round(cur_b);
       }
@@ -497,7 +491,8 @@ __global__ __launch_bounds__(TS * TS) void k_render_bwd(RenderBwdArgs A) {
         float ea;
         uint32_t et;
         win.pop_front(ea, et);
-        emit(ea, et, cur_b);
+        has = true;
+        qpos = et;
       }
       if (__any(has)) round(cur_b);
     }
