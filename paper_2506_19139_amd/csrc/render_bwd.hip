@@ -59,9 +59,11 @@ __device__ inline float wave_field_sums16(const float* gv, bool mine, int lane) 
 #pragma unroll
   for (int k = 0; k < 2; ++k) v2[k] = (b1 ? v4[k + 2] : v4[k]) + dpp_pull<kDppQuadXor2>(b1 ? v4[k] : v4[k + 2]);
   float v1 = (b0 ? v2[1] : v2[0]) + dpp_pull<kDppQuadXor1>(b0 ? v2[0] : v2[1]);
-  v1 += __shfl_xor(v1, 16);
-  v1 += __shfl_xor(v1, 32);
-  return v1;
+  // rows (0,1) and (2,3), then halves: each swap hands every lane its partner row's value
+  const auto r16 = __builtin_amdgcn_permlane16_swap(__float_as_uint(v1), __float_as_uint(v1), false, false);
+  v1 = __uint_as_float(r16[0]) + __uint_as_float(r16[1]);
+  const auto r32 = __builtin_amdgcn_permlane32_swap(__float_as_uint(v1), __float_as_uint(v1), false, false);
+  return __uint_as_float(r32[0]) + __uint_as_float(r32[1]);
 }
 
 template <int TS, int W, bool EXT>
@@ -418,9 +420,8 @@ __global__ __launch_bounds__(TS * TS) void k_render_bwd(RenderBwdArgs A) {
     while (big) {
       const int leader = __ffsll((unsigned long long)big) - 1;
       const uint32_t lp = __builtin_amdgcn_readlane(pos, leader);
-      const uint64_t m = __ballot(resident && pos == lp) & big;
-      big &= ~m;
-      const bool mine = (m >> lane) & 1ull;
+      const bool mine = resident && pos == lp;           // the whole group is big
+      big &= ~__ballot(mine);
       const float v = wave_field_sums16(gv, mine, lane);
       if (lane < kGradFields) atomicAdd(&gsl[((int)lp % NS) * kSlotStride + lane], v);
     }
