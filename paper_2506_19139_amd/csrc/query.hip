@@ -21,6 +21,7 @@
 namespace sof {
 
 constexpr int kQueryBlock = 256;
+constexpr int kQueryStage = 128;          // Gaussians staged per batch (LDS bounds the occupancy)
 
 // sched buffer layout.
 struct SchedLayout {
@@ -186,7 +187,7 @@ struct QueryArgs {
 };
 
 __global__ __launch_bounds__(kQueryBlock) void k_query_eval(QueryArgs a) {
-  __shared__ StageQ stage[kQueryBlock];
+  __shared__ StageQ stage[kQueryStage];
   __shared__ int s_blk;
   const int64_t total = *a.total_blocks;
   for (;;) {
@@ -226,10 +227,10 @@ __global__ __launch_bounds__(kQueryBlock) void k_query_eval(QueryArgs a) {
     int2 gr = a.granges[t];
     gr.x = max(0, min(gr.x, a.cap));                   // lists are read in bounds whatever bins holds
     gr.y = max(gr.x, min(gr.y, a.cap));
-    for (int gs = gr.x; gs < gr.y; gs += kQueryBlock) {
+    for (int gs = gr.x; gs < gr.y; gs += kQueryStage) {
       if (__syncthreads_count(!done) == 0) break;
       const int gi = gs + (int)threadIdx.x;
-      if (gi < gr.y) {
+      if (threadIdx.x < kQueryStage && gi < gr.y) {
         int32_t g = a.compact ? (int32_t)a.gvals[gi] : a.ggid[min(a.gvals[gi], (uint32_t)(a.cap - 1))];
         g = max(0, min(g, (int32_t)a.n - 1));
         const int64_t vg = cam_base + g;
@@ -250,7 +251,7 @@ __global__ __launch_bounds__(kQueryBlock) void k_query_eval(QueryArgs a) {
         stage[threadIdx.x] = e;
       }
       __syncthreads();
-      const int nb = min(kQueryBlock, gr.y - gs);
+      const int nb = min(kQueryStage, gr.y - gs);
       // Branch-light walk: lanes keep per-entry decisions as predicates and only wave-uniform
       // branches skip work (divergent branches cost scalar exec-mask instructions per entry,
       // which bound this loop otherwise).
