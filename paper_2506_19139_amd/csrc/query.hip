@@ -21,7 +21,9 @@
 namespace sof {
 
 constexpr int kQueryBlock = 256;
-constexpr int kQueryStage = 128;          // Gaussians staged per batch (LDS bounds the occupancy)
+constexpr int kQueryStage = 128;          // Gaussians staged per batch (LDS bounds the occupancy:
+                                          // 16.6 KB admits the eight workgroups per CU that the
+                                          // 64-VGPR bound of k_query_eval allows)
 
 // sched buffer layout.
 struct SchedLayout {
@@ -186,7 +188,7 @@ struct QueryArgs {
   float* out;
 };
 
-__global__ __launch_bounds__(kQueryBlock) void k_query_eval(QueryArgs a) {
+__global__ __launch_bounds__(kQueryBlock, 8) void k_query_eval(QueryArgs a) {
   __shared__ StageQ stage[kQueryStage];
   __shared__ int s_blk;
   const int64_t total = *a.total_blocks;
@@ -274,7 +276,7 @@ __global__ __launch_bounds__(kQueryBlock) void k_query_eval(QueryArgs a) {
         bool ok = in && (q.den > 0.f) && !(q.num > 1.0001f * e.thr * q.den);
         const bool before = sn < zx * q.den;                       // peak in front of the point
         ok = ok && (!before || sn > a.near_plane * q.den);
-        float xk = fmaxf(q.num / q.den, 0.f);
+        float xk = fmaxf(q.num * __builtin_amdgcn_rcpf(q.den), 0.f);
         const bool atx = ok && !before;                            // evaluate at the point itself
         if (__any(atx)) {
           const float wx = px - e.mu[0], wy = py - e.mu[1], wz = pz - e.mu[2];
@@ -284,7 +286,7 @@ __global__ __launch_bounds__(kQueryBlock) void k_query_eval(QueryArgs a) {
           const float xa = kHalfLog2e * fmaf(g0, g0, fmaf(g1, g1, g2 * g2));
           xk = atx ? xa : xk;
         }
-        const float al = fminf(kAlphaMax, e.o * exp2f(-xk));
+        const float al = fminf(kAlphaMax, e.o * __builtin_amdgcn_exp2f(-xk));
         ok = ok && al >= kAlphaMin;
         T = ok ? T * (1.f - al) : T;
         const bool prune = ok && (1.f - T >= cur);
