@@ -201,7 +201,7 @@ int sof_render_opacity(int64_t n, const sof_camera* h_cams, const sof_camera* d_
  * sof_render_bwd -- adjoint of sof_render_fwd, sof_render_opacity and sof_project.
  * Inputs: the same g, cameras, options, proj and bins as the forward call, its rgb,
  * normal and aux outputs, and upstream gradients d_rgb, d_acc, d_depth, d_normal (NULL =
- * zero).  d_opacity (NULL = zero) is the upstream gradient of sof_render_opacity's output;
+ * zero; d_normal requires normal, else SOF_E_ARG).  d_opacity (NULL = zero) is the upstream gradient of sof_render_opacity's output;
  * with it, depth and opacity must be the forward's depth and that output.  The depth t_r
  * at which the opacity is evaluated is held constant (like the exact-depth correction).
  * d_losses [2,H,W] (NULL = zero) is the upstream gradient of the forward's distortion and

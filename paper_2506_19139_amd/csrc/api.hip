@@ -231,6 +231,7 @@ int sof_render_bwd(const sof_gaussians* g, const sof_camera* h_cams, const sof_c
   st = fill_fwd_args(g->n, h_cams, d_cams, n_cams, opts, proj, proj_bytes, bins, bins_bytes, &b.f, &n_tiles);
   if (st) return st;
   if (!rgb || !aux) return SOF_E_ARG;
+  if (d_normal && !normal) return SOF_E_ARG;            // its suffix sums need the forward's normal
   if (g->n > 0 && (!d_means || !d_scales || !d_quats || !d_opacities || !d_sh)) return SOF_E_ARG;
   if (!grads && opts->capacity > 0) return SOF_E_ARG;
   if (grad_bytes < (size_t)opts->capacity * kGradFields * sizeof(float)) return SOF_E_WORKSPACE;

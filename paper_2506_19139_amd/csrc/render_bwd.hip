@@ -23,7 +23,7 @@ namespace sof {
 
 struct PixBwd {
   float T;
-  float cr, cg, cb, nx, ny, nz;   // prefix sums of w c and w n
+  float S;                        // prefix sum of w (g_c . c + g_n . n)
   int emitted, n_emit;
   bool done, crossed;
 };
@@ -109,7 +109,7 @@ __global__ __launch_bounds__(TS * TS, EXT ? 4 : 5) void k_render_bwd(RenderBwdAr
   const int64_t pix = (int64_t)py * width + px;
   float T_end = 1.f, Tk = 0.f;
   int n_emit = 0, kgid = -1;
-  float fr = 0, fg = 0, fb = 0, fnx = 0, fny = 0, fnz = 0;
+  float G0 = 0.f;                 // g_c . C + g_n . N - g_acc T_end over the forward's totals
   float gr = 0, gg = 0, gb = 0, ga = 0, gd = 0, gnx = 0, gny = 0, gnz = 0;
   if (inside) {
     const float* aux = a.aux + kAuxChannels * ci.pix_off;
@@ -118,12 +118,17 @@ __global__ __launch_bounds__(TS * TS, EXT ? 4 : 5) void k_render_bwd(RenderBwdAr
     kgid = __float_as_int(aux[2 * hw + pix]);
     Tk = aux[3 * hw + pix];
     const int64_t o3 = 3 * ci.pix_off;
-    fr = A.out_rgb[o3 + pix]; fg = A.out_rgb[o3 + hw + pix]; fb = A.out_rgb[o3 + 2 * hw + pix];
-    if (A.out_normal) { fnx = A.out_normal[o3 + pix]; fny = A.out_normal[o3 + hw + pix]; fnz = A.out_normal[o3 + 2 * hw + pix]; }
-    if (A.d_rgb) { gr = A.d_rgb[o3 + pix]; gg = A.d_rgb[o3 + hw + pix]; gb = A.d_rgb[o3 + 2 * hw + pix]; }
-    if (A.d_normal) { gnx = A.d_normal[o3 + pix]; gny = A.d_normal[o3 + hw + pix]; gnz = A.d_normal[o3 + 2 * hw + pix]; }
+    if (A.d_rgb) {
+      gr = A.d_rgb[o3 + pix]; gg = A.d_rgb[o3 + hw + pix]; gb = A.d_rgb[o3 + 2 * hw + pix];
+      G0 = gr * A.out_rgb[o3 + pix] + gg * A.out_rgb[o3 + hw + pix] + gb * A.out_rgb[o3 + 2 * hw + pix];
+    }
+    if (A.d_normal) {
+      gnx = A.d_normal[o3 + pix]; gny = A.d_normal[o3 + hw + pix]; gnz = A.d_normal[o3 + 2 * hw + pix];
+      G0 += gnx * A.out_normal[o3 + pix] + gny * A.out_normal[o3 + hw + pix] + gnz * A.out_normal[o3 + 2 * hw + pix];
+    }
     if (A.d_acc) ga = A.d_acc[ci.pix_off + pix];
     if (A.d_depth) gd = A.d_depth[ci.pix_off + pix];
+    G0 -= ga * T_end;
   }
   const float rx = (px + 0.5f - cam.cx) * ifx, ry = (py + 0.5f - cam.cy) * ify;
   const float dn = sqrtf(fmaf(rx, rx, fmaf(ry, ry, 1.f)));
@@ -184,7 +189,7 @@ __global__ __launch_bounds__(TS * TS, EXT ? 4 : 5) void k_render_bwd(RenderBwdAr
   }
 
   PixBwd p;
-  p.T = 1.f; p.cr = p.cg = p.cb = 0.f; p.nx = p.ny = p.nz = 0.f;
+  p.T = 1.f; p.S = 0.f;
   p.emitted = 0; p.n_emit = n_emit; p.crossed = false;
   p.done = !inside || n_emit == 0;
   Window<W> win;
@@ -234,16 +239,15 @@ __global__ __launch_bounds__(TS * TS, EXT ? 4 : 5) void k_render_bwd(RenderBwdAr
     const float w = al * Tj;
     const float om = 1.f - al;
     const float iom = __builtin_amdgcn_rcpf(om);
-    const float cr = fmaf(w, col.x, p.cr), cg = fmaf(w, col.y, p.cg), cb = fmaf(w, col.z, p.cb);
-    const float nx = fmaf(w, nrm.x, p.nx), ny = fmaf(w, nrm.y, p.ny), nz = fmaf(w, nrm.z, p.nz);
-    float dal = gr * (col.x * Tj - (fr - cr) * iom) + gg * (col.y * Tj - (fg - cg) * iom) +
-                gb * (col.z * Tj - (fb - cb) * iom);
-    dal += gnx * (nrm.x * Tj - (fnx - nx) * iom) + gny * (nrm.y * Tj - (fny - ny) * iom) +
-           gnz * (nrm.z * Tj - (fnz - nz) * iom);
-    dal += ga * T_end * iom;
+    // dF/dalpha_j = T_j f_j - (F - F_<=j) / (1 - alpha_j) for F in {colour, normal}, and
+    // T_end / (1 - alpha_j) for acc, contracted with the upstream gradients: only the scalar
+    // prefix S of w (g . f) is carried, the contracted totals sit in G0
+    const float gc = gr * col.x + gg * col.y + gb * col.z + gnx * nrm.x + gny * nrm.y + gnz * nrm.z;
+    const float S = fmaf(w, gc, p.S);
     const float testT = Tj * om;
     const bool is_k = live && !p.crossed && testT <= 0.5f;
-    if (!p.crossed && !is_k) dal -= cT * Tk * iom;
+    const float suffix = (!p.crossed && !is_k) ? (G0 - S) + cT * Tk : G0 - S;
+    float dal = gc * Tj - suffix * iom;
     const bool clamped = al >= kAlphaMax;                 // alpha = min(0.99, o G*)
     float dq = clamped ? 0.f : -0.5f * al * dal;          // dalpha/dq* = -alpha/2
     float dop = clamped ? 0.f : dal * Gs;                 // dalpha/do = G*
@@ -255,8 +259,7 @@ __global__ __launch_bounds__(TS * TS, EXT ? 4 : 5) void k_render_bwd(RenderBwdAr
       dop += do_k;
     }
     if (live) {
-      p.cr = cr; p.cg = cg; p.cb = cb;
-      p.nx = nx; p.ny = ny; p.nz = nz;
+      p.S = S;
       p.T = testT;
       if (is_k) p.crossed = true;
       if (++p.emitted >= p.n_emit) p.done = true;
