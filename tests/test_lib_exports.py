@@ -66,3 +66,15 @@ def test_host_argument_checks():
     # opacity pass: the forward's depth and aux are required
     assert L.sof_render_opacity(0, hp, hp, 1, ctypes.byref(o), None, 0, None, 0, None, None, None,
                                 None) == sof.SOF_E_ARG
+    # backward: a normal gradient needs the forward's normal (checked before any launch; with
+    # the normal given, the next check reached is the too-small partials buffer)
+    fake = ctypes.c_void_p(256)
+    big = ctypes.c_size_t(1 << 40)
+    gs0 = sof.CGaussians(0, 0, 0, None, None, None, None, None)
+
+    def bwd(normal, grads, grad_bytes):
+        return L.sof_render_bwd(ctypes.byref(gs0), hp, fake, 1, ctypes.byref(o), None, 0, fake, big, fake, normal,
+                                fake, fake, None, None, fake, None, None, None, None, None, grads, grad_bytes,
+                                None, None, None, None, None, None)
+    assert bwd(None, fake, big) == sof.SOF_E_ARG
+    assert bwd(fake, fake, 0) == sof.SOF_E_WORKSPACE
