@@ -45,8 +45,8 @@ KERNEL_SOURCES = {
     "k_render_bwd": ("render_bwd.hip", "render_common.h", "sof_internal.h", "launch.h"),
 }
 COUNTERS = {                        # kernel -> sources hash, counter KiB per dispatch
-    "k_render_bwd": {"src": "1ab13c5a01434009", "fetch_kib": 686855.6, "write_kib": 211848.8},
-    "k_render_fwd": {"src": "84790a6c5b5ea70d", "fetch_kib": 353331.6, "write_kib": 148951.8},
+    "k_render_bwd": {"src": "e4c8efd060645f0f", "fetch_kib": 686855.6, "write_kib": 211848.8},
+    "k_render_fwd": {"src": "91079bb2f90a8302", "fetch_kib": 353331.6, "write_kib": 148951.8},
 }
 COUNTER_SCALE = {"fetch": 0.50002, "write": 1.0}    # counter KiB per KiB moved by the 1 GiB copy
 

@@ -134,15 +134,15 @@ inline __host__ __device__ uint32_t float_order_bits(float f) {
   return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
 }
 
+// NDC mapping of the distortion and extent losses (near 0.2, far 100 on the ray distance)
+constexpr float kNdcNear = 0.2f, kNdcFar = 100.f;
+constexpr int kLossChannels = 4;
+
 // Depth key of the query's tile lists.  shift < 0: the exact order of the float.  Otherwise
 // a monotone integer quantisation of it: offset of the float's order bits above those of
 // 2^-10, clamped to 28 bits (32 octaves), shifted right by `shift`.  Monotone (z1 <= z2 gives
 // key(z1) <= key(z2)) and computed with integer operations only, so every kernel that
 // evaluates it on the same float gets the same key.
-// NDC mapping of the distortion and extent losses (near 0.2, far 100 on the ray distance)
-constexpr float kNdcNear = 0.2f, kNdcFar = 100.f;
-constexpr int kLossChannels = 4;
-
 constexpr float kQueryKeyBase = 0.0009765625f;
 inline __host__ __device__ int query_key_shift(int dbits) { return dbits <= 0 ? -1 : (dbits >= 28 ? 0 : 28 - dbits); }
 inline __host__ __device__ uint32_t query_depth_key(float z, int shift) {
