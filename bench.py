@@ -29,7 +29,8 @@ METRIC = "fwd+bwd ms/iter at 1M Gaussians 1080p; opacity queries/s; % HBM roofli
 HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3       # 256 CUs x 128 FP32 FMA lanes/clk (packed) x 2 x 2.4 GHz
 
-# Algorithmic FP32 work per unit of the rasteriser:
+# Algorithmic FP32 work per unit of the rasteriser (the flops the method needs, counted from
+# its formulas; the window, exec-mask, address and reduction instructions are not counted):
 FLOP_EVAL = 23      # quadric of one (pixel, list entry): offsets, b', c', den', n', cut test
 FLOP_CAND = 9       # candidate: z test, reciprocal, exponent, alpha, key
 FLOP_BLEND = 15     # one blended Gaussian: transmittance, weight, colour and normal sums
