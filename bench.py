@@ -45,10 +45,12 @@ KERNEL_SOURCES = {
     "k_render_fwd": ("render_fwd.hip", "render_common.h", "sof_internal.h", "launch.h"),
     "k_render_bwd": ("render_bwd.hip", "render_common.h", "sof_internal.h", "launch.h"),
 }
-COUNTERS = {                        # kernel -> sources hash, counter KiB per dispatch
-    "k_render_bwd": {"src": "e4c8efd060645f0f", "fetch_kib": 686855.6, "write_kib": 211848.8},
-    "k_render_fwd": {"src": "91079bb2f90a8302", "fetch_kib": 353331.6, "write_kib": 148951.8},
+COUNTERS = {                        # kernel -> sources hash, counter KiB per dispatch, SQ_INSTS_VALU
+    "k_render_bwd": {"src": "e4c8efd060645f0f", "fetch_kib": 686855.6, "write_kib": 211848.8, "valu": 2.079e9},
+    "k_render_fwd": {"src": "91079bb2f90a8302", "fetch_kib": 353331.6, "write_kib": 148951.8, "valu": 7.409e8},
 }
+VALU_CYCLES = 4                     # a wave64 vector instruction holds a 16-lane SIMD for 4 cycles
+N_SIMDS, CLOCK_GHZ = 1024, 2.4      # 256 CUs x 4 SIMDs
 COUNTER_SCALE = {"fetch": 0.50002, "write": 1.0}    # counter KiB per KiB moved by the 1 GiB copy
 
 
@@ -67,6 +69,17 @@ def measured_traffic(kernel, args):
     if not c or not default or None in COUNTER_SCALE.values() or c["src"] != kernel_source_hash(kernel):
         return None
     return round((c["fetch_kib"] / COUNTER_SCALE["fetch"] + c["write_kib"] / COUNTER_SCALE["write"]) * 1024)
+
+
+def measured_issue(kernel, args, kernel_ms):
+    """Vector-issue time of the kernel's VALU wave instructions (SQ_INSTS_VALU, same counter
+    pass rules as the traffic) on every SIMD of the chip, and its share of the measured time."""
+    c = COUNTERS.get(kernel)
+    default = (args.n, args.tile, args.window) == (1_000_000, 16, 8)
+    if not c or not default or c["src"] != kernel_source_hash(kernel):
+        return None
+    issue_ms = c["valu"] * VALU_CYCLES / (N_SIMDS * CLOCK_GHZ * 1e9) * 1e3
+    return {"valu_wave_insts": c["valu"], "issue_ms": round(issue_ms, 4), "frac": round(issue_ms / kernel_ms, 3)}
 
 
 def parse():
@@ -401,6 +414,7 @@ def main():
                 "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
                 "traffic": measured_traffic(f"k_{dominant}", args),
                 "kernel_ms": round(kern[dominant], 4),
+                "valu_issue": measured_issue(f"k_{dominant}", args, kern[dominant]),
                 "work": {"entries_tested": int(walked), "candidates": int(cands), "blended": int(n_emit),
                          "flop": int(flops)}}
 
