@@ -403,26 +403,22 @@ __global__ __launch_bounds__(TS * TS, EXT ? 4 : 5) void k_render_bwd(RenderBwdAr
 #pragma unroll
       for (int f = 0; f < kGradFields; ++f) atomicAdd(dst + f, gv[f]);
     }
-    // group the resident lanes by instance
+    // group the resident lanes by instance (wave-uniform masks: the loop is scalar work apart
+    // from one compare per group)
     uint64_t todo = __ballot(resident);
     uint64_t big = 0ull;
-    int gsize = 0;
     while (todo) {
-      const int leader = __ffsll((unsigned long long)todo) - 1;
-      const uint32_t lp = __builtin_amdgcn_readlane(pos, leader);
-      const bool mine = resident && pos == lp;
-      const uint64_t m = __ballot(mine);
-      const int c = __popcll(m);
-      if (mine) gsize = c;
-      if (c >= kGroupReduce) big |= m;
+      const uint32_t lp = __builtin_amdgcn_readlane(pos, __ffsll((unsigned long long)todo) - 1);
+      const uint64_t m = __ballot(resident && pos == lp);
+      if (__popcll(m) >= kGroupReduce) big |= m;
       todo &= ~m;
     }
-    if (resident && gsize < kGroupReduce) {
+    const int lane = (int)(threadIdx.x & 63);
+    if (resident && !((big >> lane) & 1ull)) {
       float* dst = &gsl[((int)pos % NS) * kSlotStride];
 #pragma unroll
       for (int f = 0; f < kGradFields; ++f) atomicAdd(dst + f, gv[f]);
     }
-    const int lane = (int)(threadIdx.x & 63);
     while (big) {
       const int leader = __ffsll((unsigned long long)big) - 1;
       const uint32_t lp = __builtin_amdgcn_readlane(pos, leader);
