@@ -25,7 +25,7 @@ def _camera(w=16, h=12):
                 fy=np.float32(f), cx=np.float32(w / 2), cy=np.float32(h / 2), width=w, height=h)
 
 
-def _run(seed, window, depth_mode, n=8, sh_degree=1):
+def _run(seed, window, depth_mode, n=8, sh_degree=1, tile=8):
     scene = scenes.tiny_scene(n=n, seed=seed, sh_degree=sh_degree, log_scale=-1.4)
     cam = _camera()
     W, H = cam["width"], cam["height"]
@@ -35,7 +35,7 @@ def _run(seed, window, depth_mode, n=8, sh_degree=1):
     flags = sof.SOF_DEPTH_MEDIAN if depth_mode == "median" else sof.SOF_DEPTH_GRAD_FULL
     g = sof.Gaussians.from_numpy(scene)
     C = sof.Cameras([cam])
-    rast = sof.Rasterizer(C, sof.Options(tile=8, window=window, flags=flags))
+    rast = sof.Rasterizer(C, sof.Options(tile=tile, window=window, flags=flags))
     out = rast.forward(g)
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda()
     d_rgb = dev(up[:, 0:3].T.reshape(-1))
@@ -52,10 +52,11 @@ def _run(seed, window, depth_mode, n=8, sh_degree=1):
     return gpu, fd
 
 
-@pytest.mark.parametrize("seed,window,mode", [(0, 4, "median"), (1, 4, "exact"), (2, 0, "median"), (3, 8, "exact")])
-def test_backward_matches_finite_differences(seed, window, mode):
-    print(f"[case] fd seed {seed} window {window} depth {mode}", flush=True)
-    gpu, fd = _run(seed, window, mode)
+@pytest.mark.parametrize("seed,window,mode,tile", [(0, 4, "median", 8), (1, 4, "exact", 8), (2, 0, "median", 8),
+                                                   (3, 8, "exact", 8), (4, 8, "exact", 16), (5, 16, "median", 32)])
+def test_backward_matches_finite_differences(seed, window, mode, tile):
+    print(f"[case] fd seed {seed} window {window} depth {mode} tile {tile}", flush=True)
+    gpu, fd = _run(seed, window, mode, tile=tile)
     key = {"means": "means", "scales": "scales", "quats": "quats", "opac": "opac", "sh": "sh"}
     for name in NAMES:
         ref, smooth = fd[name]
