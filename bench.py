@@ -97,6 +97,8 @@ def parse():
     ap.add_argument("--no-per-view", action="store_true",
                     help="skip the comparison against one query launch per view")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-window-sweep", action="store_true",
+                    help="skip the headline step at resort windows 4, 8 and 16")
     ap.add_argument("--no-opacity-term", action="store_true",
                     help="skip the training step with the distortion, extent and opacity-at-depth terms")
     ap.add_argument("--no-levelset", action="store_true",
@@ -319,6 +321,54 @@ def opacity_term_step(g, C, opts, rast, out, grads, target, d_acc, d_depth, d_no
                         "with all their gradients"}
 
 
+def window_sweep(g, C, capacity, target, d_acc, d_depth, d_normal, stream, steps, tile, windows=(4, 8, 16)):
+    """The headline step (project, bin_sort, forward, L1 gradient, backward) at each resort
+    window of the sweep, same scene, camera and instance capacity; kernel times from the
+    library's HIP events, step time from stream events."""
+    import torch
+    from paper_2506_19139_amd import sof
+    res = {}
+    for w in windows:
+        opts = sof.Options(tile=tile, window=w, capacity=capacity)
+        r = sof.Rasterizer(C, opts)
+        r.auto_capacity = False
+        r._alloc(g.n)
+        o = r.alloc_outputs()
+        gr = dict(means=torch.empty_like(g.means), scales=torch.empty_like(g.scales), quats=torch.empty_like(g.quats),
+                  opac=torch.empty_like(g.opac), sh=torch.empty_like(g.sh))
+        timer = sof.KernelTimer()
+        t_step = []
+
+        def step(record):
+            a = [torch.cuda.Event(enable_timing=True) for _ in range(2)] if record else None
+            if record: a[0].record(stream)
+            sof.project(g, C, opts, r.proj)
+            sof.bin_sort(g.n, C, opts, r.proj, r.bins)
+            sof.render_fwd(g.n, C, opts, r.proj, r.bins, o["rgb"], o["acc"], o["depth"], o["normal"], o["aux"])
+            d_rgb = torch.sign(o["rgb"] - target) * (1.0 / o["rgb"].numel())
+            r.backward(g, o, d_rgb, d_acc, d_depth, d_normal, grads_out=gr)
+            if record:
+                a[1].record(stream)
+                t_step.append((a[0], a[1]))
+
+        for _ in range(2):
+            step(False)
+        torch.cuda.synchronize()
+        for _ in range(steps):
+            with timer:
+                step(True)
+        torch.cuda.synchronize()
+        k_used, flags = sof.read_status(r.bins)
+        assert flags == 0 and k_used <= capacity, "instance capacity exceeded"
+        n_emit = o["aux"].view(sof.AUX_CHANNELS, C.n_pixels)[1].view(torch.int32).double().sum().item()
+        res[str(w)] = {"step_ms": round(float(np.mean([x.elapsed_time(y) for x, y in t_step])), 4),
+                       "k_render_fwd_ms": round(float(np.mean(timer.ms("render_fwd"))), 4),
+                       "k_render_bwd_ms": round(float(np.mean(timer.ms("render_bwd"))), 4),
+                       "blended_per_pixel": round(n_emit / C.n_pixels, 2)}
+        del r, o, gr
+    return res
+
+
 # --------------------------------------------------------------------------- GPU
 
 def main():
@@ -437,6 +487,12 @@ def main():
         "per_call_ms": {k: round(v, 4) for k, v in per.items()},
         "roofline": roofline,
     }
+
+    if not args.no_window_sweep:
+        log("window sweep")
+        result["window_sweep"] = window_sweep(g, C, opts.capacity, target, d_acc, d_depth, d_normal, stream,
+                                              min(args.steps, 10), args.tile)
+        torch.cuda.empty_cache()
 
     if not args.no_opacity_term:
         log("step with the opacity term")
