@@ -46,8 +46,8 @@ KERNEL_SOURCES = {
     "k_render_bwd": ("render_bwd.hip", "render_common.h", "sof_internal.h", "launch.h"),
 }
 COUNTERS = {                        # kernel -> sources hash, counter KiB per dispatch, SQ_INSTS_VALU
-    "k_render_bwd": {"src": "e4c8efd060645f0f", "fetch_kib": 686855.6, "write_kib": 211848.8, "valu": 2.079e9},
-    "k_render_fwd": {"src": "91079bb2f90a8302", "fetch_kib": 353331.6, "write_kib": 148951.8, "valu": 7.409e8},
+    "k_render_bwd": {"src": "5834443d170b975e", "fetch_kib": 686901.6, "write_kib": 211856.8, "valu": 2.0436e9},
+    "k_render_fwd": {"src": "1ca7c8e78a46d361", "fetch_kib": 353182.9, "write_kib": 148970.1, "valu": 7.409e8},
 }
 VALU_CYCLES = 4                     # a wave64 vector instruction holds a 16-lane SIMD for 4 cycles
 N_SIMDS, CLOCK_GHZ = 1024, 2.4      # 256 CUs x 4 SIMDs
