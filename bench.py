@@ -97,6 +97,8 @@ def parse():
     ap.add_argument("--no-per-view", action="store_true",
                     help="skip the comparison against one query launch per view")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-graph-step", action="store_true",
+                    help="skip the headline step replayed as one captured HIP graph")
     ap.add_argument("--no-window-sweep", action="store_true",
                     help="skip the headline step at resort windows 4, 8 and 16")
     ap.add_argument("--no-opacity-term", action="store_true",
@@ -226,6 +228,29 @@ def multiview_step(g, stream, reps=10):
             "mpx_per_s": round(cams.n_pixels / (ms * 1e-3) / 1e6, 1), "instances": int(k_used),
             "tuner_window8_ms": round(tile8[2], 3),
             "tuner_over_tile_and_window": {"tile": full[0], "window": full[1], "ms": round(full[2], 3)}}
+
+
+def graph_step(g, C, tile, window, target, d_acc, d_depth, d_normal, stream, reps=10):
+    """The headline step (same scene, camera, upstream gradients) captured once in a HIP graph
+    and replayed: what a training loop that replays the step pays per iteration."""
+    import torch
+    from paper_2506_19139_amd import sof, step
+    st = step.TrainStep(g, C, sof.Options(tile=tile, window=window), target,
+                        extra_grads=dict(acc=d_acc, depth=d_depth, normal=d_normal)).capture()
+    for _ in range(2):
+        st.replay()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(reps):
+        st.replay()
+    b.record(stream)
+    torch.cuda.synchronize()
+    k_used, flags = st.status()
+    assert flags == 0, "instance capacity exceeded in the captured step"
+    ms = a.elapsed_time(b) / reps
+    del st
+    return round(ms, 4)
 
 
 def levelset_search(qg, pts, qcams, tile, t_exact, stream, steps=8):
@@ -487,6 +512,11 @@ def main():
         "per_call_ms": {k: round(v, 4) for k, v in per.items()},
         "roofline": roofline,
     }
+
+    if not args.no_graph_step:
+        log("graph-captured step")
+        result["graph_step_ms"] = graph_step(g, C, args.tile, args.window, target, d_acc, d_depth, d_normal, stream)
+        torch.cuda.empty_cache()
 
     if not args.no_window_sweep:
         log("window sweep")
