@@ -466,10 +466,14 @@ int sof_opacity_query(const sof_gaussians* g, const sof_camera* h_cams, const so
   qa.total_blocks = &sst->aux[0];
   qa.counter = (int32_t*)&sst->aux[1];
   qa.out = opacity;
+  // persistent grid: every CU filled to the kernel's occupancy (256 CUs x 1 if a query fails;
+  // the work counter makes any grid size correct, only the speed depends on it)
   int dev = 0, cus = 0, per_cu = 0;
-  hipGetDevice(&dev);
-  hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_query_eval, kQueryBlock, 0);
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_query_eval, kQueryBlock, 0) != hipSuccess) per_cu = 0;
+  (void)hipGetLastError();                            // the launch check below sees only the launch
   const int64_t grid = (int64_t)(cus > 0 ? cus : 256) * (per_cu > 0 ? per_cu : 1);
   const int64_t maxb = S.max_blocks;
   timing_mark(kTimeQuery, 0, s);

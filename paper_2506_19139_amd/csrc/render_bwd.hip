@@ -68,9 +68,10 @@ __device__ inline float wave_field_sums16(const float* gv, bool mine, int lane) 
 
 // Five waves per SIMD (96 VGPRs; LDS allows five 256-lane workgroups per CU) hide more of the
 // gather latency than four; the variant with the optional opacity and loss terms gets four.
-// Windows above 8 keep the default (their window registers would spill under either bound).
+// Windows above 8 keep the default (their window registers would spill under either bound), and
+// so do 8x8 tiles, whose one-wave workgroups are held to three waves per SIMD by LDS.
 template <int TS, int W, bool EXT>
-__global__ __launch_bounds__(TS * TS, W <= 8 ? (EXT ? 4 : 5) : 1) void k_render_bwd(RenderBwdArgs A) {
+__global__ __launch_bounds__(TS * TS, (TS >= 16 && W <= 8) ? (EXT ? 4 : 5) : 1) void k_render_bwd(RenderBwdArgs A) {
   constexpr int NT = TS * TS;
   constexpr int B = NT < 128 ? NT : 128;         // list entries staged per batch
   constexpr int NS = 2 * B;                      // resident gradient slots (two batches)
