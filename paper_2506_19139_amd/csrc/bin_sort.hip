@@ -111,6 +111,15 @@ __device__ inline int64_t live_count(const int64_t* count, int64_t cap) {
   return k < cap ? k : cap;
 }
 
+// Keys per thread of a radix sort tile: 32-bit keys (the query's lists and point schedule, up
+// to a billion entries) use tiles of 4096, whose longer digit runs coalesce the scatter's
+// writes better; 64-bit keys keep 2048, which leaves the scatter at four waves per SIMD.
+// Workspace sizes use kSortTile, the smaller tile, so both fit.
+template <typename K>
+constexpr int sort_items() { return sizeof(K) == 4 ? 2 * kSortItems : kSortItems; }
+template <typename K>
+constexpr int sort_tile() { return sort_items<K>() * kSortThreads; }
+
 template <typename K>
 __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const K* keys, const int64_t* count, int64_t cap,
                                                              int shift, int32_t* hist, int64_t nblocks) {
@@ -119,9 +128,9 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const K* keys, cons
   for (int t = threadIdx.x; t < 4 * 256; t += kSortThreads) (&cnt[0][0])[t] = 0;
   __syncthreads();
   const int64_t n = live_count(count, cap);
-  const int64_t start = (int64_t)blockIdx.x * kSortTile + (int64_t)w * (kSortItems * 64);
+  const int64_t start = (int64_t)blockIdx.x * sort_tile<K>() + (int64_t)w * (sort_items<K>() * 64);
 #pragma unroll
-  for (int it = 0; it < kSortItems; ++it) {
+  for (int it = 0; it < sort_items<K>(); ++it) {
     const int64_t idx = start + it * 64 + lane;
     if (idx < n) {
       const int d = (int)((keys[idx] >> shift) & 0xFF);
@@ -141,20 +150,20 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const K* keys_in
   __shared__ int32_t lstart[256];      // block-local start of each digit
   __shared__ int32_t gbase[256];       // global start of this block's run of each digit
   __shared__ int32_t lw[4];
-  __shared__ K skey[kSortTile];
-  __shared__ uint32_t sval[kSortTile];
+  __shared__ K skey[sort_tile<K>()];
+  __shared__ uint32_t sval[sort_tile<K>()];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   for (int t = threadIdx.x; t < 4 * 256; t += kSortThreads) (&wc[0][0])[t] = 0;
   __syncthreads();
   const int64_t n = live_count(count, cap);
-  const int64_t bstart = (int64_t)blockIdx.x * kSortTile;
-  const int64_t start = bstart + (int64_t)w * (kSortItems * 64);
-  K key[kSortItems];
-  uint32_t val[kSortItems];
-  int rank[kSortItems];
+  const int64_t bstart = (int64_t)blockIdx.x * sort_tile<K>();
+  const int64_t start = bstart + (int64_t)w * (sort_items<K>() * 64);
+  K key[sort_items<K>()];
+  uint32_t val[sort_items<K>()];
+  int rank[sort_items<K>()];
   const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
 #pragma unroll
-  for (int it = 0; it < kSortItems; ++it) {
+  for (int it = 0; it < sort_items<K>(); ++it) {
     const int64_t idx = start + it * 64 + lane;
     const bool valid = idx < n;
     key[it] = valid ? keys_in[idx] : K(0);
@@ -191,7 +200,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const K* keys_in
   __syncthreads();
   // block-local stable sort in LDS
 #pragma unroll
-  for (int it = 0; it < kSortItems; ++it) {
+  for (int it = 0; it < sort_items<K>(); ++it) {
     const int64_t idx = start + it * 64 + lane;
     if (idx < n) {
       const int d = (int)((key[it] >> shift) & 0xFF);
@@ -202,7 +211,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const K* keys_in
   }
   __syncthreads();
   // write out: consecutive local positions of one digit go to consecutive global slots
-  const int nloc = (int)((n - bstart) < kSortTile ? (n - bstart > 0 ? n - bstart : 0) : kSortTile);
+  const int nloc = (int)((n - bstart) < sort_tile<K>() ? (n - bstart > 0 ? n - bstart : 0) : sort_tile<K>());
   for (int sidx = threadIdx.x; sidx < nloc; sidx += kSortThreads) {
     const K k = skey[sidx];
     const int d = (int)((k >> shift) & 0xFF);
@@ -215,7 +224,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const K* keys_in
 template <typename K>
 hipError_t radix_sort(K* k0, uint32_t* v0, K* k1, uint32_t* v1, const int64_t* count, int64_t cap, int bits,
                       int32_t* hist, int32_t* hist_tmp, int* out_parity, hipStream_t s) {
-  const int64_t nb = div_up(cap > 0 ? cap : 1, kSortTile);
+  const int64_t nb = div_up(cap > 0 ? cap : 1, sort_tile<K>());
   const int passes = (bits + 7) / 8;
   K* ki = k0; uint32_t* vi = v0; K* ko = k1; uint32_t* vo = v1;
   for (int p = 0; p < passes; ++p) {
