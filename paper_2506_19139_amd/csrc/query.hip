@@ -89,26 +89,43 @@ __device__ inline uint32_t quantised_depth(double z, float near_plane, int bits)
   return (uint32_t)q;
 }
 
+// The pairs of a wave's 64 points fill one contiguous range (the scan's offset of its first
+// point, of length the sum of their counts); inside it they are laid out view by view, each
+// view's visible lanes in lane order, so every store instruction writes consecutive words.
+// The order of pairs with equal keys only changes which points share a block, not a result.
 __global__ __launch_bounds__(256) void k_pv_emit(const float* pts, int64_t np, const sof_camera* cams,
                                                  const CamInfo* ci, int n_cams, float near_plane, int tile,
-                                                 const int32_t* cnt, const int64_t* off, int64_t pvcap, int dbits,
-                                                 uint32_t* keys, uint32_t* vals, StatusBlock* status) {
+                                                 const int64_t* off, int64_t pvcap, int dbits, uint32_t* keys,
+                                                 uint32_t* vals, StatusBlock* status) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= np) return;
-  const int c = cnt[p];
-  if (c == 0) return;
-  int64_t e = off[p];
-  if (e + c > pvcap) atomicOr(&status->flags, 1);
-  const float x = pts[3 * p], y = pts[3 * p + 1], z = pts[3 * p + 2];
+  const bool live = p < np;
+  if (!__any(live)) return;                           // wave-uniform: lane 0 holds the smallest p
+  const int64_t e0 = live ? off[p] : 0;
+  const int64_t base = ((int64_t)__builtin_amdgcn_readfirstlane((int)(e0 >> 32)) << 32) |
+                       (uint32_t)__builtin_amdgcn_readfirstlane((int)(e0 & 0xFFFFFFFF));
+  const int lane = (int)(threadIdx.x & 63);
+  const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  float x = 0.f, y = 0.f, z = 0.f;
+  if (live) { x = pts[3 * p]; y = pts[3 * p + 1]; z = pts[3 * p + 2]; }
+  int64_t run = 0;
+  bool over = false;
   for (int v = 0; v < n_cams; ++v) {
-    double u, w, zc;
-    if (!view_point(cams[v], near_plane, x, y, z, u, w, zc)) continue;
-    if (e >= pvcap) return;
-    const uint32_t t = (uint32_t)(ci[v].tile_off + ((int)w / tile) * ci[v].tiles_x + ((int)u / tile));
-    keys[e] = (t << dbits) | quantised_depth(zc, near_plane, dbits);
-    vals[e] = (uint32_t)p;
-    ++e;
+    double u = 0.0, w = 0.0, zc = 0.0;
+    const bool vis = live && view_point(cams[v], near_plane, x, y, z, u, w, zc);
+    const uint64_t m = __ballot(vis);
+    if (vis) {
+      const int64_t e = base + run + __popcll(m & below);
+      if (e < pvcap) {
+        const uint32_t t = (uint32_t)(ci[v].tile_off + ((int)w / tile) * ci[v].tiles_x + ((int)u / tile));
+        keys[e] = (t << dbits) | quantised_depth(zc, near_plane, dbits);
+        vals[e] = (uint32_t)p;
+      } else {
+        over = true;
+      }
+    }
+    run += __popcll(m);
   }
+  if (__any(over) && lane == 0) atomicOr(&status->flags, 1);
 }
 
 __global__ __launch_bounds__(256) void k_zero_i32(int32_t* a, int64_t n) {
@@ -418,7 +435,7 @@ int sof_opacity_query(const sof_gaussians* g, const sof_camera* h_cams, const so
   uint32_t* v1 = (uint32_t*)(sbase + S.vals1);
   if (n_points > 0)
     hipLaunchKernelGGL(k_pv_emit, dim3((unsigned)div_up(n_points, th)), dim3(th), 0, s, points, n_points, d_cams, ci,
-                       n_cams, near_plane, tile, cnt, off, pv_capacity, dbits, k0, v0, sst);
+                       n_cams, near_plane, tile, off, pv_capacity, dbits, k0, v0, sst);
   int ppar = 0;
   if ((e = radix_sort<uint32_t>(k0, v0, k1, v1, &sst->count, pv_capacity, 32, (int32_t*)(sbase + S.hist),
                                 (int32_t*)(sbase + S.hist_tmp), &ppar, s)) != hipSuccess)
