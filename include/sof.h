@@ -242,8 +242,11 @@ int sof_query_workspace_size(int64_t n, const sof_camera* h_cams, int32_t n_cams
  * passes the point's own (Eq. (15); inside the point's bucket the exact z_min decides) or
  * once the partial O_N already reaches the point's running minimum.  With
  * SOF_QUERY_LEVELSET in opts->flags the result is exact only up to the classification the
- * binary search needs: opacity[p] = O(x) when O(x) <= 0.5, otherwise a value in (0.5, O(x)].  All (view, tile, block) work items run in
- * one persistent launch.  Overwrites opacity [n_points].
+ * binary search needs: opacity[p] <= 0.5 exactly when O(x) <= 0.5, and then it is the O_N of
+ * one view, in [O(x), 0.5] (a view whose work starts after another view of the point has
+ * reported O_N <= 0.5 is skipped, so which view depends on scheduling); otherwise it is a value
+ * in (0.5, O(x)].  All (view, tile, block) work items run in one persistent launch.
+ * Overwrites opacity [n_points].
  */
 int sof_opacity_query(const sof_gaussians* g, const sof_camera* h_cams, const sof_camera* d_cams,
                       int32_t n_cams, const sof_options* opts, const float* points, int64_t n_points,

@@ -1,8 +1,9 @@
 """Level-set queries (SOF_QUERY_LEVELSET) and the binary search towards the 0.5 level set
 (sof_bisect_step), against the FP64 oracle (Sec. 3.4).
 
-A level-set query only has to classify: its value equals O(x) where O(x) <= 0.5 and lies in
-(0.5, O(x)] elsewhere.  Points whose oracle opacity is within 1e-4 of 0.5 may be classified
+A level-set query only has to classify (Sec. 3.4): where O(x) <= 0.5 its value is the O_N of
+one view, in [O(x), 0.5] (which view depends on scheduling: a view that starts after another
+view of the point reported O_N <= 0.5 is skipped), and it lies in (0.5, O(x)] elsewhere.  Points whose oracle opacity is within 1e-4 of 0.5 may be classified
 either way by float32 and are counted, not compared.  The binary search is compared on
 edges whose eight oracle midpoints all keep that distance from 0.5: same final point up to
 float32 rounding of the midpoints."""
@@ -46,8 +47,10 @@ def test_levelset_query_classifies_like_the_oracle(tile):
     print(f"  inside {int((ref > 0.5).sum())} outside {int((ref <= 0.5).sum())} near 0.5 {int(near.sum())}")
     assert np.array_equal(ls[far] > 0.5, ref[far] > 0.5)
     low = far & (ref <= 0.5)
-    assert np.abs(ls[low] - ref[low]).max(initial=0.0) <= TOL
-    assert np.all(ls <= exact + 1e-6)                  # a level-set value never exceeds O(x)
+    assert np.all(ls[low] >= ref[low] - TOL) and np.all(ls[low] <= 0.5)   # one view's O_N: an upper bound
+    hi = exact > 0.5
+    assert np.all(ls[hi] <= exact[hi] + 1e-6)          # a stopped view's partial O_N never exceeds O(x)
+    assert np.all(ls[~hi] >= exact[~hi] - 1e-6)
     assert np.array_equal(ls > 0.5, exact > 0.5)
 
 
