@@ -129,10 +129,10 @@ __device__ inline void write_pixel(const RenderFwdArgs& a, const PixFwd& p, cons
 }
 
 // Seven waves per SIMD (72 VGPRs) measure faster than the six the register count would give
-// for windows up to 8; larger windows (their registers alone would spill) and the variant with
-// the loss moments keep the default.
+// for windows up to 8, and five (96 VGPRs) than four for a window of 16 (1.90 -> 1.74 ms at
+// 1080p); a window of 32 and the variant with the loss moments keep the default.
 template <int TS, int W, bool LOSS>
-__global__ __launch_bounds__(TS * TS, (!LOSS && W <= 8) ? 7 : 1) void k_render_fwd(RenderFwdArgs a) {
+__global__ __launch_bounds__(TS * TS, LOSS ? 1 : (W <= 8 ? 7 : (W == 16 ? 5 : 1))) void k_render_fwd(RenderFwdArgs a) {
   constexpr int NT = TS * TS;
   constexpr int B = NT < 256 ? NT : 256;         // list entries staged per batch
   __shared__ StageEntry stage[B];
