@@ -209,7 +209,9 @@ int sof_render_opacity(int64_t n, const sof_camera* h_cams, const sof_camera* d_
  * follow App. C.1 (dL/dalpha front to back from the stored totals) and C.2.
  * Each pixel's forward order is replayed front to back; suffix sums come from the stored
  * totals.  Writes (overwrites) d_means [n,3], d_scales [n,3], d_quats [n,4], d_opacities
- * [n], d_sh [n,K,3].  `grads` is scratch.  Deterministic: per-instance partials are reduced
+ * [n], d_sh [n,K,3].  `grads` is scratch.  Reproducible to float rounding, not bitwise: a
+ * tile's pixels add into each instance's partials with LDS float atomics, whose order follows
+ * the scheduling of the tile's waves; the per-instance partials of a Gaussian are then summed
  * in a fixed order.
  */
 int sof_render_bwd(const sof_gaussians* g, const sof_camera* h_cams, const sof_camera* d_cams,

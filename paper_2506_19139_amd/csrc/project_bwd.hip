@@ -1,7 +1,7 @@
 // Reduction of per-instance gradient partials and the chain rule back to the Gaussian
 // parameters (adjoint of sof_project).  One thread per Gaussian: for every camera it sums
-// the partials of the Gaussian's instances (contiguous in emission order, summed in a fixed
-// order, so the result is deterministic), maps the camera-space (mu_c, P_c) gradients to
+// the partials of the Gaussian's instances (contiguous in emission order, summed in that fixed
+// order, so this sum adds no order dependence of its own), maps the camera-space (mu_c, P_c) gradients to
 // world space, adds the view-dependent colour and normal terms, and finally chains the
 // world precision P = R diag(1/s^2) R^T to scales and the quaternion.
 #include "launch.h"
