@@ -488,10 +488,14 @@ def main():
     roofline = {"bound": "alu", "kernel": f"k_{dominant}", "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
                 "traffic": measured_traffic(f"k_{dominant}", args),
+                "hbm_frac": None,
                 "kernel_ms": round(kern[dominant], 4),
                 "valu_issue": measured_issue(f"k_{dominant}", args, kern[dominant]),
                 "work": {"entries_tested": int(walked), "candidates": int(cands), "blended": int(n_emit),
                          "flop": int(flops)}}
+
+    if roofline["traffic"]:                # measured HBM bytes over the kernel time, against 8 TB/s
+        roofline["hbm_frac"] = round(roofline["traffic"] / (kern[dominant] * 1e-3) / (HBM_PEAK_GBS * 1e9), 4)
 
     result = {
         "metric": METRIC,
