@@ -46,7 +46,7 @@ KERNEL_SOURCES = {
     "k_render_bwd": ("render_bwd.hip", "render_common.h", "sof_internal.h", "launch.h"),
 }
 COUNTERS = {                        # kernel -> sources hash, counter KiB per dispatch, SQ_INSTS_VALU
-    "k_render_bwd": {"src": "2d8fed9ec3f7b6f3", "fetch_kib": 686727.8, "write_kib": 211851.3, "valu": 2.0436e9},
+    "k_render_bwd": {"src": "4b61ebdef2b233f7", "fetch_kib": 686727.8, "write_kib": 211851.3, "valu": 2.0436e9},
     "k_render_fwd": {"src": "c5159a6cd52e64d1", "fetch_kib": 353514.4, "write_kib": 148958.0, "valu": 7.409e8},
 }
 VALU_CYCLES = 4                     # a wave64 vector instruction holds a 16-lane SIMD for 4 cycles

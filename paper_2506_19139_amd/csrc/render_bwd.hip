@@ -284,9 +284,10 @@ __global__ __launch_bounds__(TS * TS, (TS >= 16 && W <= 8) ? (EXT ? 4 : 5) : 1) 
     // and of the extent e = sqrt((E^2 - q*) / A) / (|d~| s*^2)
     if constexpr (EXT) {
       if (loss_on) {
-        const float t = dn * sstar;
-        const float d = kNdcFar * (t - kNdcNear) / ((kNdcFar - kNdcNear) * t);
-        const float ndcp = kKappa / (t * t);
+        // hardware reciprocals (1 ulp) throughout: nothing here decides an integer
+        const float t = dn * sstar, it = __builtin_amdgcn_rcpf(t);
+        const float d = (kNdcFar / (kNdcFar - kNdcNear)) * (t - kNdcNear) * it;
+        const float ndcp = kKappa * it * it;
         const float Tn = testT;
         // L_dist = sum_ij w_i w_j (d_i - d_j)^2: dL/dw_k = 2 (A (d_k - mu)^2 + M), and the
         // suffix sum_{i>k} w_i dL/dw_i = 2 (A (M - prefix_k) + M (A - A_k))
@@ -294,30 +295,31 @@ __global__ __launch_bounds__(TS * TS, (TS >= 16 && W <= 8) ? (EXT ? 4 : 5) : 1) 
         const float cd = 2.f * (Atot * dc * dc + Mtot);
         Mp = fmaf(w * dc, dc, Mp);
         const float Sd = 2.f * (Atot * (Mtot - Mp) + Mtot * (Atot - (1.f - Tn)));
-        float dal_x = g_dist * (cd * Tj - Sd / (1.f - al));
+        float dal_x = g_dist * (cd * Tj - Sd * iom);
         ds += g_dist * 4.f * w * Atot * dc * ndcp * dn;                   // dL/dd_k = 4 w_k A (d_k - mu)
         const float qs = xs * (2.f * kLn2);
         const float u = fmaxf(2.f * logf(255.f * o) - qs, 1e-12f);
-        const float e = sqrtf(u / Am) / (dn * sstar * sstar);
+        const float iu = __builtin_amdgcn_rcpf(u), iAm = __builtin_amdgcn_rcpf(Am);
+        const float e = sqrtf(u * iAm) * it * __builtin_amdgcn_rcpf(sstar);
         Ep = fmaf(w, e, Ep);
-        dal_x += g_ext * kKappa * (e * Tj - (Etot - Ep) / (1.f - al));
-        const float ce = g_ext * kKappa * w;
-        dq -= ce * e / (2.f * u);
-        dA -= ce * e / (2.f * Am);
-        ds -= ce * 2.f * e / sstar;
-        dop += ce * e / (u * o);
-        if (al < kAlphaMax) {
+        dal_x += g_ext * kKappa * (e * Tj - (Etot - Ep) * iom);
+        const float ce = g_ext * kKappa * w, cee = ce * e;
+        dq -= 0.5f * cee * iu;
+        dA -= 0.5f * cee * iAm;
+        ds -= 2.f * cee * it * dn;                                          // 1 / s* = |d~| / t
+        dop += cee * iu * __builtin_amdgcn_rcpf(o);
+        if (al < kAlphaMax) {                                                // alpha / o = G*
           dq -= 0.5f * al * dal_x;
-          dop += dal_x * al / o;
+          dop += dal_x * Gs;
         }
       }
     }
     // opacity at the rendered depth, peak in front of x: alpha_j(x) is the blend alpha
     if constexpr (EXT) {
       if (opa_on && sstar <= s_r && al < kAlphaMax) {
-        const float dl = gopaP / (1.f - al);
+        const float dl = gopaP * iom;
         dq -= 0.5f * al * dl;
-        dop += dl * al / o;
+        dop += dl * Gs;                                                      // alpha / o = G*
       }
     }
     const float dq2 = 2.f * dq;
@@ -358,7 +360,7 @@ __global__ __launch_bounds__(TS * TS, (TS >= 16 && W <= 8) ? (EXT ? 4 : 5) : 1) 
         const float araw = o * exp2f(-(xs + kHalfLog2e * Am * dsr * dsr));
         const float ax = fminf(kAlphaMax, araw);
         if (ax >= kAlphaMin && s_r > near_plane && araw < kAlphaMax) {
-          const float dl = gopaP / (1.f - ax);
+          const float dl = gopaP * __builtin_amdgcn_rcpf(1.f - ax);
           const float dqx = -0.5f * ax * dl, dqx2 = 2.f * dqx;
           const float mzr = mz - s_r;
           const float ux = mzr * dmx - s_r * dnx, uy = mzr * dmy - s_r * dny, uz = mzr;
@@ -371,7 +373,7 @@ __global__ __launch_bounds__(TS * TS, (TS >= 16 && W <= 8) ? (EXT ? 4 : 5) : 1) 
           gv[6] += dqx * uy * uy;
           gv[7] += dqx * uy * uz;
           gv[8] += dqx * uz * uz;
-          gv[9] += dl * ax / o;
+          gv[9] += dl * ax * __builtin_amdgcn_rcpf(o);
         }
       }
     }
