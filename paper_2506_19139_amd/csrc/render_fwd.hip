@@ -53,16 +53,17 @@ __device__ inline void loss_terms(PixFwd& p, float w, float sstar, uint32_t gid,
   const float4 r0 = geom[4 * vg], r1 = geom[4 * vg + 1], r2 = geom[4 * vg + 2], r3 = geom[4 * vg + 3];
   const float2 d2 = pixel_offset(r0, px, py);
   const Quad q = quad_terms(r1.x, r1.y, r1.z, r1.w, r2.x, r2.y, r2.z, r2.w, d2.x, d2.y);
-  const float qs = fmaxf(q.num / q.den, 0.f) * (2.f * kLn2);          // q*
-  const float u = fmaxf(2.f * logf(255.f * r3.y) - qs, 0.f);          // E^2 - q*
-  const float e = sqrtf(u / (r3.w * q.den)) / (dn * sstar * sstar);
-  const float t = dn * sstar;
-  const float d = kNdcFar * (t - kNdcNear) / ((kNdcFar - kNdcNear) * t);
+  // hardware reciprocals (1 ulp): these values only enter the losses, never a decision
+  const float qs = fmaxf(q.num * __builtin_amdgcn_rcpf(q.den), 0.f) * (2.f * kLn2);   // q*
+  const float u = fmaxf(2.f * logf(255.f * r3.y) - qs, 0.f);                           // E^2 - q*
+  const float t = dn * sstar, it = __builtin_amdgcn_rcpf(t);
+  const float e = sqrtf(u * __builtin_amdgcn_rcpf(r3.w * q.den)) * it * __builtin_amdgcn_rcpf(sstar);
+  const float d = (kNdcFar / (kNdcFar - kNdcNear)) * (t - kNdcNear) * it;
   // weighted running mean and second moment (numerically stable; the distortion
   // sum_ij w_i w_j (d_i - d_j)^2 = 2 A sum w (d - mean)^2 would cancel as 2 (A DD - D^2))
   p.A += w;
   const float delta = d - p.mu;
-  p.mu = fmaf(w / p.A, delta, p.mu);
+  p.mu = fmaf(w * __builtin_amdgcn_rcpf(p.A), delta, p.mu);
   p.M = fmaf(w * delta, d - p.mu, p.M);
   p.E = fmaf(w, e, p.E);
 }
