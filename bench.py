@@ -46,8 +46,8 @@ KERNEL_SOURCES = {
     "k_render_bwd": ("render_bwd.hip", "render_common.h", "sof_internal.h", "launch.h"),
 }
 COUNTERS = {                        # kernel -> sources hash, counter KiB per dispatch, SQ_INSTS_VALU
-    "k_render_bwd": {"src": "4b61ebdef2b233f7", "fetch_kib": 686727.8, "write_kib": 211851.3, "valu": 2.0436e9},
-    "k_render_fwd": {"src": "8c995cfdd16c6afb", "fetch_kib": 353514.4, "write_kib": 148958.0, "valu": 7.409e8},
+    "k_render_bwd": {"src": "e43c02028bc3aae5", "fetch_kib": 686727.8, "write_kib": 211851.3, "valu": 2.0436e9},
+    "k_render_fwd": {"src": "c50ee27622f6d01e", "fetch_kib": 353514.4, "write_kib": 148958.0, "valu": 7.409e8},
 }
 VALU_CYCLES = 4                     # a wave64 vector instruction holds a 16-lane SIMD for 4 cycles
 N_SIMDS, CLOCK_GHZ = 1024, 2.4      # 256 CUs x 4 SIMDs

@@ -297,8 +297,8 @@ __global__ __launch_bounds__(TS * TS, (TS >= 16 && W <= 8) ? (EXT ? 4 : 5) : 1) 
         const float Sd = 2.f * (Atot * (Mtot - Mp) + Mtot * (Atot - (1.f - Tn)));
         float dal_x = g_dist * (cd * Tj - Sd * iom);
         ds += g_dist * 4.f * w * Atot * dc * ndcp * dn;                   // dL/dd_k = 4 w_k A (d_k - mu)
-        const float qs = xs * (2.f * kLn2);
-        const float u = fmaxf(2.f * logf(255.f * o) - qs, 1e-12f);
+        // E^2 - q* = 2 ln 2 (log2(255 o) - x*), log2(255 o) being the record's 1/255 cut
+        const float u = fmaxf((2.f * kLn2) * (r3.z - xs), 1e-12f);
         const float iu = __builtin_amdgcn_rcpf(u), iAm = __builtin_amdgcn_rcpf(Am);
         const float e = sqrtf(u * iAm) * it * __builtin_amdgcn_rcpf(sstar);
         Ep = fmaf(w, e, Ep);

@@ -54,8 +54,9 @@ __device__ inline void loss_terms(PixFwd& p, float w, float sstar, uint32_t gid,
   const float2 d2 = pixel_offset(r0, px, py);
   const Quad q = quad_terms(r1.x, r1.y, r1.z, r1.w, r2.x, r2.y, r2.z, r2.w, d2.x, d2.y);
   // hardware reciprocals (1 ulp): these values only enter the losses, never a decision
-  const float qs = fmaxf(q.num * __builtin_amdgcn_rcpf(q.den), 0.f) * (2.f * kLn2);   // q*
-  const float u = fmaxf(2.f * logf(255.f * r3.y) - qs, 0.f);                           // E^2 - q*
+  // E^2 - q* = 2 ln 2 (log2(255 o) - x*): the record keeps log2(255 o) (the 1/255 cut)
+  const float xs = fmaxf(q.num * __builtin_amdgcn_rcpf(q.den), 0.f);
+  const float u = (2.f * kLn2) * fmaxf(r3.z - xs, 0.f);
   const float t = dn * sstar, it = __builtin_amdgcn_rcpf(t);
   const float e = sqrtf(u * __builtin_amdgcn_rcpf(r3.w * q.den)) * it * __builtin_amdgcn_rcpf(sstar);
   const float d = (kNdcFar / (kNdcFar - kNdcNear)) * (t - kNdcNear) * it;
