@@ -183,6 +183,34 @@ int sof_render_fwd(int64_t n, const sof_camera* h_cams, const sof_camera* d_cams
                    float* losses, hipStream_t stream);
 
 /*
+ * sof_render_order -- the per-pixel order of Sec. 3.1 (level-0 tile list, then the per-pixel
+ * resort window), as a debug output for checking it entry by entry.
+ * Runs the forward rasteriser with the same n, cameras, options, proj and bins as
+ * sof_render_fwd (its decisions are those of sof_render_fwd: the same kernel code with stores
+ * added) and writes no image.  slot [sum of W H] int32 (device) names, for each pixel, a row
+ * of the output arrays; pixels whose slot lies outside [0, n_slots) are not written.  Each
+ * row holds up to max_entries (M) entries:
+ *   stream_ids  [n_slots, M] int32  Gaussian index of each candidate (alpha >= 1/255, peak
+ *                                   beyond the near plane) in the order the window received
+ *                                   them, up to where the pixel stopped
+ *   stream_keys [n_slots, M] float  its key: the view z of the peak (the ray distance t* is
+ *                                   the key times |(x_n, y_n, 1)|, so both order alike)
+ *   emit_ids    [n_slots, M] int32  Gaussian index of each entry in the order it left the
+ *                                   window; the first n_emitted were blended, one more means
+ *                                   that entry stopped the pixel (T would drop below 1e-4)
+ *   counts      [n_slots, 2] int32  number of candidates fed and of entries out (may exceed
+ *                                   M; only the first M of each list are written)
+ * Two pixels must not share a slot.  Caller-owned device buffers; entries beyond the counts
+ * are left as they were.  SOF_E_ARG for a null slot or counts, or null lists with
+ * max_entries > 0.
+ */
+int sof_render_order(int64_t n, const sof_camera* h_cams, const sof_camera* d_cams, int32_t n_cams,
+                     const sof_options* opts, const void* proj, size_t proj_bytes, const void* bins,
+                     size_t bins_bytes, const int32_t* slot, int64_t n_slots, int32_t max_entries,
+                     int32_t* stream_ids, float* stream_keys, int32_t* emit_ids, int32_t* counts,
+                     hipStream_t stream);
+
+/*
  * sof_render_opacity -- Sec. 3.3 (direct opacity-field supervision).
  * A second pass after sof_render_fwd (same n, cameras, options, proj and bins; its depth
  * and aux outputs as inputs): for each pixel with a 0.5 crossing, opacity = O_N(x) at

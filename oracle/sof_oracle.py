@@ -387,6 +387,50 @@ def blend(cands: Candidates, order, scene_opac, color, normal, bg=(0.0, 0.0, 0.0
                        emitted, emitted_t, weights)
 
 
+def pixel_terms(scene: Scene, v: CameraView, px, py, ids):
+    """t*, peak view z and alpha = min(0.99, o G*) of the listed Gaussians on the ray of pixel
+    (px, py), whether or not they pass the candidate test (Eq. (9)-(10))."""
+    ids = np.asarray(ids, np.int64)
+    d, dc = v.cam.pixel_ray(px, py)
+    A, B, C = ray_abc(v.prec[ids], scene.means[ids], v.cam.center, d)
+    tstar = -B / (2.0 * A)
+    gstar = np.exp(-0.5 * np.maximum(0.0, C - B * B / (4.0 * A)))
+    alpha = np.minimum(ALPHA_MAX, scene.opac[ids] * gstar)
+    return tstar, tstar / np.linalg.norm(dc), alpha, gstar, A
+
+
+def blend_sequence(scene: Scene, v: CameraView, px, py, order_ids, k, bg=(0.0, 0.0, 0.0)):
+    """Eq. (1) over a given sequence of Gaussians with a given crossing Gaussian.
+
+    Every Gaussian of `order_ids` is blended in that order (no candidate, order or
+    termination decision is taken here) and the exact depth (R4) is taken on Gaussian `k`
+    (-1: no crossing) with T_k the transmittance in front of it.  This lets a result whose
+    discrete decisions were taken elsewhere (for instance in float32, near a threshold) be
+    recomputed in float64 with exactly those decisions."""
+    ids = [int(i) for i in order_ids]
+    T = 1.0
+    rgb, nrm = np.zeros(3), np.zeros(3)
+    depth = median = 0.0
+    T_k = 0.0
+    weights, ts = [], []
+    if ids:
+        tstar, _, alpha, gstar, A = pixel_terms(scene, v, px, py, ids)
+    for j, gid in enumerate(ids):
+        a = alpha[j]
+        w = a * T
+        rgb += w * v.color[gid]
+        nrm += w * v.normal[gid]
+        if gid == k:
+            T_k = T
+            depth = exact_depth(tstar[j], gstar[j], A[j], scene.opac[gid], T)
+            median = tstar[j]
+        weights.append(w)
+        ts.append(float(tstar[j]))
+        T *= 1.0 - a
+    rgb = rgb + np.asarray(bg, np.float64) * T
+    return PixelResult(rgb, 1.0 - T, depth, median, nrm, T, len(ids), int(k), T_k, ids, ts, weights)
+
+
 def render_pixel(scene: Scene, v: CameraView, px, py, window, bg=(0.0, 0.0, 0.0), subset=None):
     """One pixel: candidates -> hierarchical order (window >= 2**30 means full sort) -> blend."""
     cands = pixel_candidates(scene, v, px, py, subset)

@@ -182,6 +182,30 @@ int sof_render_fwd(int64_t n, const sof_camera* h_cams, const sof_camera* d_cams
   return hip_status(e);
 }
 
+int sof_render_order(int64_t n, const sof_camera* h_cams, const sof_camera* d_cams, int32_t n_cams,
+                     const sof_options* opts, const void* proj, size_t proj_bytes, const void* bins, size_t bins_bytes,
+                     const int32_t* slot, int64_t n_slots, int32_t max_entries, int32_t* stream_ids,
+                     float* stream_keys, int32_t* emit_ids, int32_t* counts, hipStream_t stream) {
+  RenderFwdArgs a;
+  int64_t n_tiles = 0;
+  int st = fill_fwd_args(n, h_cams, d_cams, n_cams, opts, proj, proj_bytes, bins, bins_bytes, &a, &n_tiles);
+  if (st) return st;
+  if (!slot || n_slots < 0 || max_entries < 0) return SOF_E_ARG;
+  if (n_slots > 0 && (!counts || (max_entries > 0 && (!stream_ids || !stream_keys || !emit_ids)))) return SOF_E_ARG;
+  if (n_slots > 0 && max_entries > 0 && n_slots > INT64_MAX / max_entries) return SOF_E_ARG;
+  a.dump.slot = slot;
+  a.dump.n_slots = n_slots;
+  a.dump.max_entries = max_entries;
+  a.dump.stream_ids = stream_ids;
+  a.dump.stream_keys = stream_keys;
+  a.dump.emit_ids = emit_ids;
+  a.dump.counts = counts;
+  if (trace_enabled())
+    fprintf(stderr, "[sof] render_order tiles=%lld slots=%lld max=%d\n", (long long)n_tiles, (long long)n_slots,
+            max_entries);
+  return hip_status(launch_render_fwd(a, opts->tile, opts->window, n_tiles, stream));
+}
+
 int sof_filter3d(const sof_gaussians* g, const sof_camera* h_cams, const sof_camera* d_cams, int32_t n_cams,
                  float near_plane, float k, float* var, float* scales_out, float* opacities_out, hipStream_t stream) {
   if (!g || g->n < 0 || g->n >= (int64_t(1) << 31) || n_cams < 0 || !(near_plane > 0.f) || !(k >= 0.f))

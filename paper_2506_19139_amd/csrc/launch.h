@@ -28,6 +28,17 @@ hipError_t launch_query_bin_sort(int64_t n, const sof_camera* d_cams, int n_cams
 hipError_t launch_cam_table(const sof_camera* d_cams, int n_cams, int tile, CamInfo* out, StatusBlock* status,
                             hipStream_t s);
 
+// Per-pixel order output of sof_render_order (all null: off).
+struct OrderDump {
+  const int32_t* slot;      // [P] output slot of each pixel; outside [0, n_slots): none
+  int64_t n_slots;
+  int32_t max_entries;      // M: entries kept per slot and list
+  int32_t* stream_ids;      // [n_slots, M] candidates in the order the window received them
+  float* stream_keys;       // [n_slots, M] their keys (view z of the peak)
+  int32_t* emit_ids;        // [n_slots, M] entries in the order they left the window
+  int32_t* counts;          // [n_slots, 2] candidates fed, entries out (may exceed M)
+};
+
 struct RenderFwdArgs {
   int64_t n;
   const sof_camera* cams;
@@ -48,6 +59,7 @@ struct RenderFwdArgs {
   float* normal;
   float* aux;
   float* losses;            // [4, P]: distortion, extent, sum w d, sum w d^2 (null: off)
+  OrderDump dump;
 };
 
 struct RenderBwdArgs {

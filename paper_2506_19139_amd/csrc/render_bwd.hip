@@ -297,10 +297,13 @@ __global__ __launch_bounds__(TS * TS, (TS >= 16 && W <= 8) ? (EXT ? 4 : 5) : 1) 
         const float Sd = 2.f * (Atot * (Mtot - Mp) + Mtot * (Atot - (1.f - Tn)));
         float dal_x = g_dist * (cd * Tj - Sd * iom);
         ds += g_dist * 4.f * w * Atot * dc * ndcp * dn;                   // dL/dd_k = 4 w_k A (d_k - mu)
-        // E^2 - q* = 2 ln 2 (log2(255 o) - x*), log2(255 o) being the record's 1/255 cut
-        const float u = fmaxf((2.f * kLn2) * (r3.z - xs), 1e-12f);
-        const float iu = __builtin_amdgcn_rcpf(u), iAm = __builtin_amdgcn_rcpf(Am);
-        const float e = sqrtf(u * iAm) * it * __builtin_amdgcn_rcpf(sstar);
+        // E^2 - q* = 2 ln 2 (log2(255 o) - x*), log2(255 o) being the record's 1/255 cut.
+        // Where that is not positive (an alpha that passed the cut by rounding) the forward
+        // clamps it to 0, so the extent is 0 there and has no direct terms either
+        const float uraw = (2.f * kLn2) * (r3.z - xs);
+        const bool ext_pos = uraw > 0.f;
+        const float iu = __builtin_amdgcn_rcpf(ext_pos ? uraw : 1.f), iAm = __builtin_amdgcn_rcpf(Am);
+        const float e = ext_pos ? sqrtf(uraw * iAm) * it * __builtin_amdgcn_rcpf(sstar) : 0.f;
         Ep = fmaf(w, e, Ep);
         dal_x += g_ext * kKappa * (e * Tj - (Etot - Ep) * iom);
         const float ce = g_ext * kKappa * w, cee = ce * e;

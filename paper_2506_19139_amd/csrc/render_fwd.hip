@@ -130,11 +130,20 @@ __device__ inline void write_pixel(const RenderFwdArgs& a, const PixFwd& p, cons
   }
 }
 
+// Kernel variants: the plain forward, the forward with the loss moments, and the forward
+// that also writes the per-pixel order (debug output of sof_render_order; the same code
+// with stores added, so its decisions are those of the plain forward).
+enum FwdMode { kFwdPlain = 0, kFwdLoss = 1, kFwdDump = 2 };
+
 // Seven waves per SIMD (72 VGPRs) measure faster than the six the register count would give
 // for windows up to 8, and five (96 VGPRs) than four for a window of 16 (1.90 -> 1.74 ms at
-// 1080p); a window of 32 and the variant with the loss moments keep the default.
-template <int TS, int W, bool LOSS>
-__global__ __launch_bounds__(TS * TS, LOSS ? 1 : (W <= 8 ? 7 : (W == 16 ? 5 : 1))) void k_render_fwd(RenderFwdArgs a) {
+// 1080p); a window of 32 and the variants with the loss moments or the order output keep
+// the default.
+template <int TS, int W, int MODE>
+__global__ __launch_bounds__(TS * TS, MODE != kFwdPlain ? 1 : (W <= 8 ? 7 : (W == 16 ? 5 : 1))) void k_render_fwd(
+    RenderFwdArgs a) {
+  constexpr bool LOSS = MODE == kFwdLoss;
+  constexpr bool DUMP = MODE == kFwdDump;
   constexpr int NT = TS * TS;
   constexpr int B = NT < 256 ? NT : 256;         // list entries staged per batch
   __shared__ StageEntry stage[B];
@@ -169,6 +178,35 @@ __global__ __launch_bounds__(TS * TS, LOSS ? 1 : (W <= 8 ? 7 : (W == 16 ? 5 : 1)
   p.done = !inside;
   Window<W> win;
   win.init();
+  // order output: this pixel's slot (-1: none), candidates fed to the window and entries
+  // that left it
+  int64_t dslot = -1;
+  int n_fed = 0, n_out = 0;
+  if constexpr (DUMP) {
+    if (inside) {
+      const int32_t sl = a.dump.slot[ci.pix_off + (int64_t)py * width + px];
+      if (sl >= 0 && sl < a.dump.n_slots) dslot = sl;
+    }
+  }
+  auto record_fed = [&](uint32_t tag, float key) {
+    if constexpr (DUMP) {
+      if (dslot >= 0) {
+        if (n_fed < a.dump.max_entries) {
+          a.dump.stream_ids[dslot * a.dump.max_entries + n_fed] = (int32_t)tag;
+          a.dump.stream_keys[dslot * a.dump.max_entries + n_fed] = key;
+        }
+        ++n_fed;
+      }
+    }
+  };
+  auto record_out = [&](uint32_t tag) {
+    if constexpr (DUMP) {
+      if (dslot >= 0) {
+        if (n_out < a.dump.max_entries) a.dump.emit_ids[dslot * a.dump.max_entries + n_out] = (int32_t)tag;
+        ++n_out;
+      }
+    }
+  };
 
   for (int bs = rg.x; bs < rg.y; bs += B) {
     if (__syncthreads_count(!p.done) == 0) break;
@@ -193,7 +231,9 @@ __global__ __launch_bounds__(TS * TS, LOSS ? 1 : (W <= 8 ? 7 : (W == 16 ? 5 : 1)
         ++p.cands;
         float ea, ek;
         uint32_t et;
+        record_fed(__float_as_uint(e.tag), key);
         if (win.push(key, al, __float_as_uint(e.tag), ea, et, ek)) {
+          record_out(et);
           const float w = blend(p, ea, et, a.app, cam_base);
           if constexpr (LOSS) {
             if (w > 0.f) loss_terms(p, w, ek, et, a.geom, cam_base, px, py, dn);
@@ -207,6 +247,7 @@ __global__ __launch_bounds__(TS * TS, LOSS ? 1 : (W <= 8 ? 7 : (W == 16 ? 5 : 1)
       float ea, ek;
       uint32_t et;
       win.pop_front(ea, et, ek);
+      record_out(et);
       const float w = blend(p, ea, et, a.app, cam_base);
       if constexpr (LOSS) {
         if (w > 0.f) loss_terms(p, w, ek, et, a.geom, cam_base, px, py, dn);
@@ -214,20 +255,26 @@ __global__ __launch_bounds__(TS * TS, LOSS ? 1 : (W <= 8 ? 7 : (W == 16 ? 5 : 1)
     }
   }
   if (!inside) return;
+  if constexpr (DUMP) {
+    if (dslot >= 0) {
+      a.dump.counts[2 * dslot] = n_fed;
+      a.dump.counts[2 * dslot + 1] = n_out;
+    }
+  }
   write_pixel<LOSS>(a, p, cam, ci, cam_base, px, py);
 }
 
-template <int TS, bool LOSS>
+template <int TS, int MODE>
 static hipError_t launch_fwd_tsl(const RenderFwdArgs& a, int window, int64_t n_tiles, hipStream_t s) {
   const dim3 grid((unsigned)n_tiles), block(TS * TS);
   switch (window) {
-    case 0: hipLaunchKernelGGL((k_render_fwd<TS, 0, LOSS>), grid, block, 0, s, a); break;
-    case 1: hipLaunchKernelGGL((k_render_fwd<TS, 1, LOSS>), grid, block, 0, s, a); break;
-    case 2: hipLaunchKernelGGL((k_render_fwd<TS, 2, LOSS>), grid, block, 0, s, a); break;
-    case 4: hipLaunchKernelGGL((k_render_fwd<TS, 4, LOSS>), grid, block, 0, s, a); break;
-    case 8: hipLaunchKernelGGL((k_render_fwd<TS, 8, LOSS>), grid, block, 0, s, a); break;
-    case 16: hipLaunchKernelGGL((k_render_fwd<TS, 16, LOSS>), grid, block, 0, s, a); break;
-    case 32: hipLaunchKernelGGL((k_render_fwd<TS, 32, LOSS>), grid, block, 0, s, a); break;
+    case 0: hipLaunchKernelGGL((k_render_fwd<TS, 0, MODE>), grid, block, 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_render_fwd<TS, 1, MODE>), grid, block, 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_render_fwd<TS, 2, MODE>), grid, block, 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_render_fwd<TS, 4, MODE>), grid, block, 0, s, a); break;
+    case 8: hipLaunchKernelGGL((k_render_fwd<TS, 8, MODE>), grid, block, 0, s, a); break;
+    case 16: hipLaunchKernelGGL((k_render_fwd<TS, 16, MODE>), grid, block, 0, s, a); break;
+    case 32: hipLaunchKernelGGL((k_render_fwd<TS, 32, MODE>), grid, block, 0, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -235,7 +282,8 @@ static hipError_t launch_fwd_tsl(const RenderFwdArgs& a, int window, int64_t n_t
 
 template <int TS>
 static hipError_t launch_fwd_ts(const RenderFwdArgs& a, int window, int64_t n_tiles, hipStream_t s) {
-  return a.losses ? launch_fwd_tsl<TS, true>(a, window, n_tiles, s) : launch_fwd_tsl<TS, false>(a, window, n_tiles, s);
+  if (a.dump.slot) return launch_fwd_tsl<TS, kFwdDump>(a, window, n_tiles, s);
+  return a.losses ? launch_fwd_tsl<TS, kFwdLoss>(a, window, n_tiles, s) : launch_fwd_tsl<TS, kFwdPlain>(a, window, n_tiles, s);
 }
 
 bool render_supported(int tile, int window) {

@@ -66,6 +66,8 @@ _SIGS = {
                                     ctypes.c_size_t, _P]),
     "sof_render_fwd": (ctypes.c_int, [ctypes.c_int64, _P, _P, ctypes.c_int32, _P, _P, ctypes.c_size_t, _P,
                                       ctypes.c_size_t, _P, _P, _P, _P, _P, _P, _P]),
+    "sof_render_order": (ctypes.c_int, [ctypes.c_int64, _P, _P, ctypes.c_int32, _P, _P, ctypes.c_size_t, _P,
+                                        ctypes.c_size_t, _P, ctypes.c_int64, ctypes.c_int32, _P, _P, _P, _P, _P]),
     "sof_render_opacity": (ctypes.c_int, [ctypes.c_int64, _P, _P, ctypes.c_int32, _P, _P, ctypes.c_size_t, _P,
                                           ctypes.c_size_t, _P, _P, _P, _P]),
     "sof_render_bwd": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, _P, _P, ctypes.c_size_t, _P, ctypes.c_size_t,
@@ -229,6 +231,24 @@ def render_fwd(n, cams: Cameras, opts: Options, proj, bins, rgb=None, acc=None, 
                                 _ptr(losses), _stream()), "sof_render_fwd")
 
 
+def render_order(n, cams: Cameras, opts: Options, proj, bins, slot, n_slots, max_entries):
+    """Per-pixel order output (sof_render_order) for the pixels whose slot is in [0, n_slots):
+    (stream_ids, stream_keys, emit_ids [n_slots, M], counts [n_slots, 2]) device tensors."""
+    dev = slot.device
+    M = int(max_entries)
+    stream_ids = torch.full((max(n_slots, 1), max(M, 1)), -1, dtype=torch.int32, device=dev)
+    stream_keys = torch.full((max(n_slots, 1), max(M, 1)), float("nan"), dtype=torch.float32, device=dev)
+    emit_ids = torch.full((max(n_slots, 1), max(M, 1)), -1, dtype=torch.int32, device=dev)
+    counts = torch.zeros((max(n_slots, 1), 2), dtype=torch.int32, device=dev)
+    if not (slot.dtype == torch.int32 and slot.is_contiguous() and slot.numel() == cams.n_pixels):
+        raise SofError("slot must be a contiguous int32 tensor with one entry per pixel")
+    o = opts.c_struct()
+    _check(lib().sof_render_order(n, cams.hp(), cams.dp(), len(cams), ctypes.byref(o), _ptr(proj), proj.numel(),
+                                  _ptr(bins), bins.numel(), _ptr(slot), int(n_slots), M, _ptr(stream_ids),
+                                  _ptr(stream_keys), _ptr(emit_ids), _ptr(counts), _stream()), "sof_render_order")
+    return stream_ids[:n_slots], stream_keys[:n_slots], emit_ids[:n_slots], counts[:n_slots]
+
+
 def render_opacity(n, cams: Cameras, opts: Options, proj, bins, depth, aux, opacity):
     o = opts.c_struct()
     _check(lib().sof_render_opacity(n, cams.hp(), cams.dp(), len(cams), ctypes.byref(o), _ptr(proj), proj.numel(),
@@ -379,6 +399,9 @@ class Rasterizer:
         self.proj = self.bins = self.grads = None
         self._n = -1
         self.last_count = 0
+        # bumped by every prepare(): proj and bins then hold another frame's lists, so a
+        # backward saved against an older generation would replay the wrong frame
+        self.generation = 0
 
     def _alloc(self, n):
         p, b, g = workspace_size(n, self.cams, self.opts)
@@ -394,6 +417,7 @@ class Rasterizer:
         n = g.n
         if self.opts.capacity <= 0:
             self.opts.capacity = max(1024, 4 * n * len(self.cams))
+        self.generation += 1
         self._alloc(n)
         project(g, self.cams, self.opts, self.proj)
         bin_sort(n, self.cams, self.opts, self.proj, self.bins)
@@ -422,6 +446,34 @@ class Rasterizer:
         render_fwd(g.n, self.cams, self.opts, self.proj, self.bins, out["rgb"], out["acc"], out["depth"],
                    out["normal"], out["aux"], out["losses"] if losses else None)
         return out
+
+    def order(self, g: Gaussians, pixels_per_cam, max_entries=512):
+        """Per-pixel order of the last forward for the listed pixels ((px, py) per camera).
+        Returns, per camera, a list of dicts: stream ids / keys (candidates in the order the
+        window received them), emitted ids (in the order they left it), as numpy arrays."""
+        slot = torch.full((self.cams.n_pixels,), -1, dtype=torch.int32)
+        where, off, n_slots = [], 0, 0
+        for (w, h), pixels in zip(self.cams.sizes, pixels_per_cam):
+            for px, py in pixels:
+                slot[off + py * w + px] = n_slots
+                where.append(n_slots)
+                n_slots += 1
+            off += w * h
+        sid, skey, eid, cnt = render_order(g.n, self.cams, self.opts, self.proj, self.bins, slot.to(self.device),
+                                           n_slots, max_entries)
+        sid, skey, eid, cnt = (t.cpu().numpy() for t in (sid, skey, eid, cnt))
+        res, i = [], 0
+        for pixels in pixels_per_cam:
+            cam_res = []
+            for _ in pixels:
+                nf, no = int(cnt[i, 0]), int(cnt[i, 1])
+                if nf > max_entries or no > max_entries:
+                    raise SofError(f"order output truncated ({nf} fed, {no} out > {max_entries})")
+                cam_res.append(dict(stream_ids=sid[i, :nf].copy(), stream_keys=skey[i, :nf].copy(),
+                                    emit_ids=eid[i, :no].copy()))
+                i += 1
+            res.append(cam_res)
+        return res
 
     def opacity(self, g: Gaussians, out):
         """Opacity field at each pixel's rendered depth (second pass after forward); stored in
@@ -466,13 +518,22 @@ class SofRasterize(torch.autograd.Function):
         g = Gaussians(means.contiguous(), scales.contiguous(), quats.contiguous(), opac.contiguous(),
                       sh.contiguous(), int(sh_degree))
         out = rast.forward(g)
-        ctx.rast, ctx.g, ctx.out = rast, g, out
+        # the backward replays from the rasterizer's proj / bins buffers: remember which
+        # frame they hold, so that a later forward through the same rasterizer is caught
+        ctx.rast, ctx.generation, ctx.sh_degree = rast, rast.generation, int(sh_degree)
+        ctx.save_for_backward(g.means, g.scales, g.quats, g.opac, g.sh, out["rgb"], out["normal"], out["aux"])
         return out["rgb"], out["acc"], out["depth"], out["normal"]
 
     @staticmethod
     def backward(ctx, d_rgb, d_acc, d_depth, d_normal):
+        if ctx.rast.generation != ctx.generation:
+            raise SofError("SofRasterize.backward: the rasterizer rendered another frame after this forward "
+                           "(its tile lists were overwritten); use one Rasterizer per pending backward")
+        means, scales, quats, opac, sh, rgb, normal, aux = ctx.saved_tensors
+        g = Gaussians(means, scales, quats, opac, sh, ctx.sh_degree)
+        out = dict(rgb=rgb, normal=normal, aux=aux)
         c = lambda t: None if t is None else t.contiguous()
-        gr = ctx.rast.backward(ctx.g, ctx.out, c(d_rgb), c(d_acc), c(d_depth), c(d_normal))
+        gr = ctx.rast.backward(g, out, c(d_rgb), c(d_acc), c(d_depth), c(d_normal))
         return gr["means"], gr["scales"], gr["quats"], gr["opac"], gr["sh"], None, None
 
 

@@ -26,7 +26,7 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_helpers import TOL_ABS, compare_images, unpack
+from gpu_helpers import TOL_ABS, PixelReport, compare_images, unpack
 from oracle import sof_oracle as O
 from paper_2506_19139_amd import scenes, sof
 
@@ -79,25 +79,31 @@ def _sample_pixels(cam, n, seed):
     return [(int(x), int(y)) for x, y in zip(rng.integers(0, cam["width"], n), rng.integers(0, cam["height"], n))]
 
 
-def _forward_parity(cams, pixels_per_cam, host, cam_ids, scene, window):
-    """Compare the sampled pixels of every camera with the oracle on that camera's
-    sub-scene."""
-    totals = [0, 0, 0]
+def _to_local(ids):
+    """Map whole-scene Gaussian ids to indices of the sub-scene `ids` (sorted); an id outside
+    the sub-scene maps to -1 (it cannot reach the ray, so the order check then fails)."""
+    def f(a):
+        a = np.asarray(a, np.int64)
+        j = np.searchsorted(ids, a)
+        j = np.minimum(j, len(ids) - 1)
+        return np.where(ids[j] == a, j, -1)
+    return f
+
+
+def _forward_parity(cams, pixels_per_cam, host, cam_ids, scene, window, order):
+    """Verify the sampled pixels of every camera against the oracle on that camera's
+    sub-scene (order: the GPU's per-pixel order output for them, per camera)."""
+    total = PixelReport()
     for ci, (cam, pixels, ids) in enumerate(zip(cams, pixels_per_cam, cam_ids)):
         gpu = unpack(host, cams, ci)
         sc = O.Scene.from_arrays(**scenes.subset_scene(scene, ids))
         oc = O.Camera.from_arrays(**cam)
         v = O.view(sc, oc)
         orc = O.render(sc, oc, window, pixels=pixels)
-        k = np.asarray(orc["k"])
-        orc["k"] = np.where(k >= 0, ids[np.maximum(k, 0)], -1)
-        bad, unflagged, frag, worst = compare_images(gpu, orc, sc, v, pixels)
-        totals[0] += bad
-        totals[1] += unflagged
-        totals[2] += frag
-        print(f"  camera {ci} {cam['width']}x{cam['height']}: {len(ids)} Gaussians, mismatching {bad} "
-              f"fragile {frag} worst {worst}")
-    return totals
+        print(f"  camera {ci} {cam['width']}x{cam['height']}: {len(ids)} Gaussians")
+        total.add(compare_images(gpu, orc, sc, v, pixels, order[ci], window, to_local=_to_local(ids)))
+    print(f"  all cameras: {total}")
+    return total
 
 
 def _directional_fd(scene, cams, pixels_per_cam, weights, cam_ids, grads, window, n_dirs=3, seed=0, h=1e-6,
@@ -201,8 +207,8 @@ def _run_training_case(scene, cams, tile, window, pixels_per_cam, seed, label, o
     cam_ids = [np.nonzero(_ray_superset(scene, cam, pixels, reach))[0] for cam, pixels in zip(cams, pixels_per_cam)]
     print(f"[case] {label}: {sum(map(len, cam_ids))} (camera, Gaussian) pairs reach the "
           f"{sum(map(len, pixels_per_cam))} sampled rays", flush=True)
-    bad, unflagged, frag = _forward_parity(cams, pixels_per_cam, host, cam_ids, scene, window)
-    assert unflagged == 0, (label, bad, frag)
+    order = r.order(g, pixels_per_cam)
+    _forward_parity(cams, pixels_per_cam, host, cam_ids, scene, window, order).check()
     weights, d_rgb, d_acc, d_depth, d_nrm = _upstream(cams, pixels_per_cam, seed)
     opa_terms, d_opa, lw, d_losses = None, None, None, None
     if opa:

@@ -1,8 +1,10 @@
 """GPU parity of project -> bin_sort -> render_fwd against the FP64 oracle, called
 through the C ABI.  Tolerances: 1e-4 absolute on rgb / acc / normal, 1e-4 relative on
-depth, bit-exact integer stages (tile lists, ranges, emitted counts, crossing index);
-pixels where float32 and float64 may legitimately take a different discrete decision
-(near-tie or near-threshold, see gpu_helpers.fragile) are counted and reported."""
+depth, bit-exact integer stages (tile lists, ranges, the per-pixel order given the GPU's own
+keys, emitted counts, crossing index).  A pixel where float32 takes a different discrete
+decision than float64 passes only at a near-tie or near-threshold and only if the oracle fed
+the GPU's decisions reproduces the GPU's outputs; such pixels are counted against a stated
+cap (gpu_helpers.PixelReport)."""
 import numpy as np
 import pytest
 import torch
@@ -19,20 +21,35 @@ def _small():
     return scenes.small_scene(), scenes.small_camera()
 
 
-@pytest.mark.parametrize("window", [8, 0, 4, 16])
-def test_small_scene_full_frame_parity(window):
+@pytest.fixture(scope="module")
+def small_oracle():
+    """The float64 oracle over every pixel of the small scene, per window (tile independent)."""
     scene, cam = _small()
-    print(f"[case] small scene 1000 Gaussians 64x64 tile 16 window {window}", flush=True)
-    r, g, C, opts, out, host = gpu_render(scene, [cam], tile=16, window=window)
-    gpu = unpack(host, [cam])
     sc, oc = oracle_scene_cam(scene, cam)
-    v = O.view(sc, oc)
     pixels = [(x, y) for y in range(cam["height"]) for x in range(cam["width"])]
-    orc = O.render(sc, oc, window, pixels=pixels)
-    bad, unflagged, frag, worst = compare_images(gpu, orc, sc, v, pixels)
-    print(f"window {window}: mismatching pixels {bad} (near-tie/threshold {frag}), worst unflagged {worst}")
-    assert unflagged == 0, worst
-    assert frag <= 3
+    return scene, cam, sc, oc, O.view(sc, oc), pixels, {}
+
+
+@pytest.mark.parametrize("window", sof.WINDOWS)
+def test_small_scene_full_frame_order_and_parity(small_oracle, window):
+    """Every pixel of the 1000-Gaussian 64x64 scene at every window and tile size: the emitted
+    order equals the oracle's hierarchical resort of the GPU's own candidate stream and keys
+    bit for bit, and the outputs match the float64 oracle (Sec. 3.1, Eq. (1))."""
+    scene, cam, sc, oc, v, pixels, cache = small_oracle
+    if window not in cache:
+        cache[window] = O.render(sc, oc, window, pixels=pixels)
+    orc = cache[window]
+    for tile in sof.TILES:
+        print(f"[case] small scene 1000 Gaussians 64x64 tile {tile} window {window}", flush=True)
+        r, g, C, opts, out, host = gpu_render(scene, [cam], tile=tile, window=window)
+        gpu = unpack(host, [cam])
+        order = r.order(g, [pixels])[0]
+        rep = compare_images(gpu, orc, sc, v, pixels, order, window)
+        rep.check()
+        # with the window covering every candidate the order is the exact sort by t*
+        if window == 32:
+            n_full = sum(1 for od in order if len(od["stream_ids"]) <= 32)
+            assert n_full > 0.9 * len(pixels)
 
 
 def test_tile_lists_bit_exact():
@@ -89,9 +106,10 @@ def test_background_and_median_depth():
     pixels = [(x, y) for y in range(0, 64, 5) for x in range(0, 64, 5)]
     orc = O.render(sc, oc, 8, pixels=pixels, bg=bg)
     orc["depth"] = orc["median_depth"]
+    orc["depth_is_median"], orc["bg"] = True, bg
     v = O.view(sc, oc)
-    bad, unflagged, frag, worst = compare_images(gpu, orc, sc, v, pixels)
-    assert unflagged == 0, worst
+    rep = compare_images(gpu, orc, sc, v, pixels, r.order(g, [pixels])[0], 8)
+    rep.check()
 
 
 def test_near_plane_and_off_screen_gaussians():
@@ -113,9 +131,8 @@ def test_near_plane_and_off_screen_gaussians():
     v = O.view(sc, oc)
     pixels = [(x, y) for y in range(40) for x in range(48)]
     orc = O.render(sc, oc, 4, pixels=pixels)
-    bad, unflagged, frag, worst = compare_images(gpu, orc, sc, v, pixels)
-    print(f"near-plane: mismatching {bad} fragile {frag} worst {worst}")
-    assert unflagged == 0, worst
+    rep = compare_images(gpu, orc, sc, v, pixels, r.order(g, [pixels])[0], 4)
+    rep.check()
 
 
 def test_empty_and_fully_culled():
@@ -153,6 +170,6 @@ def test_clusters_sampled_pixels():
     rng = np.random.default_rng(0)
     pixels = [(int(x), int(y)) for x, y in zip(rng.integers(0, 1280, 48), rng.integers(0, 720, 48))]
     orc = O.render(sc, oc, 8, pixels=pixels)
-    bad, unflagged, frag, worst = compare_images(gpu, orc, sc, v, pixels)
-    print(f"clusters: mismatching {bad} fragile {frag} worst {worst}, K={r.last_count}")
-    assert unflagged == 0, worst
+    print(f"clusters: K={r.last_count}")
+    rep = compare_images(gpu, orc, sc, v, pixels, r.order(g, [pixels])[0], 8)
+    rep.check()

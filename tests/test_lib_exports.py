@@ -78,3 +78,27 @@ def test_host_argument_checks():
                                 None, None, None, None, None, None)
     assert bwd(None, fake, big) == sof.SOF_E_ARG
     assert bwd(fake, fake, 0) == sof.SOF_E_WORKSPACE
+
+
+def test_render_order_argument_checks():
+    """sof_render_order rejects a missing slot map, missing counts, negative sizes and null
+    lists with max_entries > 0, before anything is enqueued."""
+    L = sof.lib()
+    cam = sof.CCamera()
+    cam.R[:] = [1, 0, 0, 0, 1, 0, 0, 0, 1]
+    cam.fx = cam.fy = 50.0
+    cam.cx = cam.cy = 8.0
+    cam.width = cam.height = 16
+    hp = ctypes.cast(ctypes.pointer(cam), ctypes.c_void_p)
+    o = sof.Options(tile=16, window=8, capacity=1024).c_struct()
+    fake = ctypes.c_void_p(256)
+    big = ctypes.c_size_t(1 << 40)
+
+    def order(slot, n_slots, m, lists, counts):
+        return L.sof_render_order(0, hp, hp, 1, ctypes.byref(o), None, 0, fake, big, slot, n_slots, m,
+                                  lists, lists, lists, counts, None)
+    assert order(None, 4, 8, fake, fake) == sof.SOF_E_ARG
+    assert order(fake, -1, 8, fake, fake) == sof.SOF_E_ARG
+    assert order(fake, 4, -1, fake, fake) == sof.SOF_E_ARG
+    assert order(fake, 4, 8, None, fake) == sof.SOF_E_ARG
+    assert order(fake, 4, 8, fake, None) == sof.SOF_E_ARG

@@ -102,6 +102,37 @@ def test_two_separated_gaussians(o1, o2):
         assert r.depth == 0.0
 
 
+def test_blend_sequence_in_reversed_order_and_with_a_given_crossing():
+    """blend_sequence takes the order and the crossing as given: two separated Gaussians fed
+    back to front give the closed form of that order, and the exact depth is taken on the
+    Gaussian named as the crossing with the transmittance in front of it."""
+    o1, o2, s = 0.6, 0.3, 0.05
+    c1, c2 = np.array([0.9, 0.1, 0.3]), np.array([0.2, 0.8, 0.6])
+    sc = O.Scene(np.array([[0, 0, 3.0], [0, 0, 5.0]]), np.full((2, 3), s), np.tile([1.0, 0, 0, 0], (2, 1)),
+                 np.array([o1, o2]), np.stack([(c1 - 0.5) / scenes.SH_C0, (c2 - 0.5) / scenes.SH_C0])[:, None, :], 0)
+    cam = axis_camera(0.0)
+    v = O.view(sc, cam)
+    r = O.blend_sequence(sc, v, 0, 0, [1, 0], k=0)
+    np.testing.assert_allclose(r.rgb, c2 * o2 + c1 * o1 * (1 - o2), atol=1e-12)
+    assert r.acc == pytest.approx(1 - (1 - o1) * (1 - o2), abs=1e-12)
+    assert r.T_k == pytest.approx(1 - o2, abs=1e-12)
+    # T_k (1 - o1 G(t)) = 1/2 on the near side of Gaussian 0: G = (T_k - 1/2) / (T_k o1)
+    g = (r.T_k - 0.5) / (r.T_k * o1)
+    assert r.depth == pytest.approx(3.0 - s * math.sqrt(2 * math.log(1 / g)), abs=1e-12)
+    none = O.blend_sequence(sc, v, 0, 0, [0, 1], k=-1)
+    assert none.depth == 0.0 and none.k == -1
+
+
+def test_blend_sequence_reproduces_the_oracle_render(small_render):
+    sc, cam, ref = small_render
+    v = O.view(sc, cam)
+    for (px, py), r in zip(ref["pixels"], ref["results"]):
+        b = O.blend_sequence(sc, v, px, py, r.order, r.k)
+        np.testing.assert_allclose(b.rgb, r.rgb, atol=1e-13)
+        assert b.acc == pytest.approx(r.acc, abs=1e-13)
+        assert b.depth == pytest.approx(r.depth, abs=1e-12)
+
+
 # --------------------------------------------------------------------------- P3
 
 def test_opacity_field_is_order_independent():
@@ -253,6 +284,58 @@ def test_sh_basis_is_orthonormal_and_matches_low_orders():
     np.testing.assert_allclose(Y[:7, 2], k1 * d[:, 2], atol=1e-14)          # Y_1^0 = k z
     np.testing.assert_allclose(Y[:7, 3], -k1 * d[:, 0], atol=1e-14)         # Condon-Shortley
     np.testing.assert_allclose(Y[:7, 1], -k1 * d[:, 1], atol=1e-14)
+
+
+def _sh_table(d):
+    """Real spherical harmonics of degrees 2 and 3 written out as polynomials of the unit
+    direction (x, y, z), in the column order l^2 + l + m, m = -l..l, with the Condon-Shortley
+    phase: each entry is (-1)^m times the usual real-form polynomial (odd positive m and
+    odd negative m flip sign), as for degree 1 where Y_1^1 = -sqrt(3/4pi) x."""
+    x, y, z = d[:, 0], d[:, 1], d[:, 2]
+    pi = math.pi
+    c2a = 0.5 * math.sqrt(15 / pi)
+    c2b = 0.25 * math.sqrt(5 / pi)
+    c2c = 0.25 * math.sqrt(15 / pi)
+    c3a = 0.25 * math.sqrt(35 / (2 * pi))
+    c3b = 0.5 * math.sqrt(105 / pi)
+    c3c = 0.25 * math.sqrt(21 / (2 * pi))
+    c3d = 0.25 * math.sqrt(7 / pi)
+    c3e = 0.25 * math.sqrt(105 / pi)
+    return {
+        4: c2a * x * y,                               # l=2, m=-2
+        5: -c2a * y * z,                              # m=-1 (sign flipped)
+        6: c2b * (3 * z * z - 1),                     # m=0
+        7: -c2a * x * z,                              # m=1 (sign flipped)
+        8: c2c * (x * x - y * y),                     # m=2
+        9: -c3a * y * (3 * x * x - y * y),            # l=3, m=-3 (sign flipped)
+        10: c3b * x * y * z,                          # m=-2
+        11: -c3c * y * (5 * z * z - 1),               # m=-1 (sign flipped)
+        12: c3d * z * (5 * z * z - 3),                # m=0
+        13: -c3c * x * (5 * z * z - 1),               # m=1 (sign flipped)
+        14: c3e * z * (x * x - y * y),                # m=2
+        15: -c3a * x * (x * x - 3 * y * y),           # m=3 (sign flipped)
+    }
+
+
+def test_sh_basis_degrees_2_and_3_match_the_written_out_polynomials():
+    """Orthonormality cannot see a sign flip or an m <-> -m swap; explicit values can.  The
+    directions are generic (no coordinate zero, |x| != |y|), so every polynomial is non-zero
+    and no two columns agree up to sign."""
+    rng = np.random.default_rng(3)
+    d = rng.standard_normal((12, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    d = np.concatenate([d, [[0.48, 0.6, 0.64], [-0.36, 0.48, -0.8]]])
+    Y = O.sh_basis(3, d)
+    for col, ref in _sh_table(d).items():
+        np.testing.assert_allclose(Y[:, col], ref, atol=1e-13, err_msg=f"column {col}")
+    # and the basis is evaluated at the direction from the camera centre to the mean
+    sc = one_gaussian((0.48, 0.6, 0.64), 0.1, 0.5)
+    sc = O.Scene(sc.means, sc.scales, sc.quats, sc.opac, np.zeros((1, 16, 3)), 3)
+    sc.sh[0, 13, 1] = 0.7                                        # Y_3^1, green only
+    col = O.gaussian_colors(sc, np.zeros(3))[0]
+    expect = 0.5 + 0.7 * _sh_table(np.array([[0.48, 0.6, 0.64]]))[13][0]
+    assert col[1] == pytest.approx(max(expect, 0.0), abs=1e-13)
+    assert col[0] == pytest.approx(0.5, abs=1e-15) and col[2] == pytest.approx(0.5, abs=1e-15)
 
 
 def test_degree0_colour_roundtrip():
@@ -411,6 +494,62 @@ def test_query_min_over_views_and_unobserved():
     assert both == pytest.approx(min(a, b))
     outside = np.array([100.0, 0.0, 5.0])
     assert O.opacity_field(sc, [front, back], [outside])[0] == 1.0
+
+
+# near-plane rules (tau_n = 0.2): a camera at the origin looking down +z, pixel 0's ray at
+# tan(theta) = 1/2, one isotropic Gaussian on the z axis at depth D.  On that ray the peak
+# lies at ray distance t* = D cos(theta), whose view z is D cos(theta)^2 = 0.8 D.  A mean at
+# D = 0.24 is in front of the near plane (not culled) but its peak is behind it (z 0.192);
+# at D = 0.26 the peak's z is 0.208.  The ray distance t* itself is above 0.2 in both
+# cases, so reading the rule on t* instead of the view z would fail these pins.
+NEAR_THETA = math.atan(0.5)
+
+
+@pytest.mark.parametrize("D,is_candidate", [(0.24, False), (0.26, True), (0.2499, False), (0.2501, True)])
+def test_candidate_needs_the_peak_beyond_the_near_plane(D, is_candidate):
+    s, o = 0.1, 0.8
+    sc = one_gaussian((0, 0, D), s, o)
+    cam = axis_camera(NEAR_THETA)
+    v = O.view(sc, cam)
+    assert v.live[0]                                              # the mean is at z = D > 0.2
+    tstar = D * math.cos(NEAR_THETA)
+    assert tstar > O.NEAR                                         # the slip would keep it
+    c = O.pixel_candidates(sc, v, 0, 0)
+    assert (len(c.idx) == 1) == is_candidate
+    if is_candidate:
+        assert c.tstar[0] == pytest.approx(tstar, abs=1e-13)
+        assert c.alpha[0] == pytest.approx(o * math.exp(-(D * math.sin(NEAR_THETA)) ** 2 / (2 * s * s)), abs=1e-13)
+    r = O.render_pixel(sc, v, 0, 0, 8)
+    assert r.acc == pytest.approx(c.alpha[0] if is_candidate else 0.0, abs=1e-13)
+
+
+@pytest.mark.parametrize("D", [0.24, 0.26])
+def test_query_counts_a_gaussian_only_if_its_evaluated_point_is_beyond_the_near_plane(D):
+    s, o = 0.1, 0.8
+    sc = one_gaussian((0, 0, D), s, o)
+    cam = axis_camera(NEAR_THETA)
+    c, sn = math.cos(NEAR_THETA), math.sin(NEAR_THETA)
+    d = np.array([sn, 0.0, c])
+    # x beyond the peak (view z 0.5): t_eval = t*, whose view z is 0.8 D
+    x = (0.5 / c) * d
+    assert O.point_view_valid(cam, x)
+    got = O.opacity_field(sc, [cam], [x])[0]
+    peak = o * math.exp(-(D * sn) ** 2 / (2 * s * s))
+    assert got == pytest.approx(peak if D == 0.26 else 0.0, abs=1e-13)
+    # x at view z 0.205 (> 0.2, so the camera sees it): for D = 0.26 it lies in front of the
+    # peak (z 0.208) and the Gaussian is evaluated at x itself, q = |x - mu|^2 / s^2; for
+    # D = 0.24 the peak (z 0.192) is in front of x, is the evaluated point, and is behind
+    # the near plane, so nothing is counted (testing x's own z instead would count it)
+    x2 = (0.205 / c) * d
+    assert O.point_view_valid(cam, x2)
+    t = np.linalg.norm(x2)
+    q = (t * t - 2 * t * D * c + D * D) / (s * s)
+    expect2 = o * math.exp(-0.5 * q) if D == 0.26 else 0.0
+    assert O.opacity_field(sc, [cam], [x2])[0] == pytest.approx(expect2, abs=1e-13)
+    # a point at view z 0.19 is not seen by the camera at all: unobserved, opacity 1
+    x3 = (0.19 / c) * d
+    assert not O.point_view_valid(cam, x3)
+    assert O.opacity_field(sc, [cam], [x3])[0] == 1.0
 
 
 def test_zmin_early_stop_is_exact():
