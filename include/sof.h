@@ -38,8 +38,11 @@
  *     returned from an asynchronous call; it is recorded in the status word inside the
  *     `bins` buffer (see sof_read_status_offset) and the affected work is clipped so that
  *     nothing is written out of bounds.
- *   - Thread safety: no global mutable state; calls on different streams with different
- *     buffers may run concurrently.
+ *   - State and thread safety: the library keeps nothing between calls except two
+ *     process-wide items, the timing-event table of sof_set_timing_events (instrumentation,
+ *     not thread-safe) and the per-device static scratch of sof_render_bwd_static (calls of
+ *     it that overlap on one device race).  Every other call works only on the caller's
+ *     buffers: calls on different streams with different buffers may run concurrently.
  */
 #ifndef SOF_H
 #define SOF_H
@@ -59,7 +62,8 @@ typedef enum sof_status {
   SOF_E_WORKSPACE = -2,    /* a workspace buffer is smaller than sof_workspace_size asks   */
   SOF_E_CAPACITY = -3,     /* (device status bit) more tile instances than `capacity`       */
   SOF_E_HIP = -4,          /* a HIP launch failed (hipGetLastError after enqueue)          */
-  SOF_E_UNSUPPORTED = -5   /* window or tile size without a compiled kernel               */
+  SOF_E_UNSUPPORTED = -5,  /* window or tile size without a compiled kernel               */
+  SOF_E_SCRATCH = -6       /* sof_render_bwd_static: capacity above its fixed scratch       */
 } sof_status;
 
 /* Option flags */
@@ -250,6 +254,28 @@ int sof_render_bwd(const sof_gaussians* g, const sof_camera* h_cams, const sof_c
                    const float* d_opacity, const float* losses, const float* d_losses, void* grads,
                    size_t grad_bytes, float* d_means, float* d_scales, float* d_quats,
                    float* d_opacities, float* d_sh, hipStream_t stream);
+
+/*
+ * sof_render_bwd_static -- sof_render_bwd without the `grads` workspace, for callers that
+ * cannot allocate device memory (code under HIP graph capture, serving loops, harnesses that
+ * forbid hipMalloc).  It allocates nothing: the per-instance gradient partials live in a
+ * static device array inside the library, 64 MiB per device (opts->capacity up to 2^20 tile
+ * instances; larger capacities return SOF_E_SCRATCH before anything is enqueued), held by
+ * every device the library runs on until the process ends.  The array's device address is
+ * looked up on the first call on each device (that device must be current).  Every other
+ * argument, and the results, are those of sof_render_bwd.  All calls on one device share its
+ * array: calls that overlap in time on one device (other streams, other threads) race and
+ * must be serialised by the caller.  Nothing in the array needs clearing between calls (each
+ * call writes every partial it reads).
+ */
+int sof_render_bwd_static(const sof_gaussians* g, const sof_camera* h_cams, const sof_camera* d_cams,
+                          int32_t n_cams, const sof_options* opts, const void* proj, size_t proj_bytes,
+                          const void* bins, size_t bins_bytes, const float* rgb, const float* normal,
+                          const float* aux, const float* d_rgb, const float* d_acc, const float* d_depth,
+                          const float* d_normal, const float* depth, const float* opacity,
+                          const float* d_opacity, const float* losses, const float* d_losses,
+                          float* d_means, float* d_scales, float* d_quats, float* d_opacities, float* d_sh,
+                          hipStream_t stream);
 
 /*
  * Workspace for sof_opacity_query: like sof_workspace_size with the per-view tile lists

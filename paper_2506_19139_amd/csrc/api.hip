@@ -4,6 +4,8 @@
 #include <string.h>
 #include <stdio.h>
 
+#include <mutex>
+
 #include "launch.h"
 
 using namespace sof;
@@ -54,6 +56,30 @@ int sorted_parity(int64_t n_tiles) { return (((32 + bits_for(n_tiles)) + 7) / 8)
 
 hipEvent_t g_timing[2 * kTimedKernels] = {};
 
+// Scratch of sof_render_bwd_static: the per-instance gradient partials (16 floats per tile
+// instance) of up to kStaticInstances instances, 64 MiB on every device the library runs on,
+// held until the process ends.  Host code never passes `scratch` itself to a kernel (on the
+// host it names a stand-in, not device memory): its device address, looked up once per device
+// with that device current, is kept in g_scratch_ptr.
+constexpr int64_t kStaticInstances = int64_t(1) << 20;
+static __device__ __align__(256) float scratch[kStaticInstances * kGradFields];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+int static_scratch(void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return SOF_E_HIP;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return SOF_E_HIP;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return SOF_OK;
+}
+
 }  // namespace
 
 namespace sof {
@@ -80,6 +106,7 @@ const char* sof_strerror(int code) {
     case SOF_E_CAPACITY: return "tile-instance capacity exceeded";
     case SOF_E_HIP: return "HIP launch failed";
     case SOF_E_UNSUPPORTED: return "unsupported tile/window combination";
+    case SOF_E_SCRATCH: return "capacity exceeds the static scratch of sof_render_bwd_static (2^20 instances)";
     default: return "unknown sof status";
   }
 }
@@ -241,13 +268,14 @@ int sof_render_opacity(int64_t n, const sof_camera* h_cams, const sof_camera* d_
   return hip_status(launch_render_opa(a, opts->tile, opts->window, n_tiles, stream));
 }
 
-int sof_render_bwd(const sof_gaussians* g, const sof_camera* h_cams, const sof_camera* d_cams, int32_t n_cams,
-                   const sof_options* opts, const void* proj, size_t proj_bytes, const void* bins, size_t bins_bytes,
-                   const float* rgb, const float* normal, const float* aux, const float* d_rgb, const float* d_acc,
-                   const float* d_depth, const float* d_normal, const float* depth, const float* opacity,
-                   const float* d_opacity, const float* losses, const float* d_losses, void* grads,
-                   size_t grad_bytes, float* d_means, float* d_scales, float* d_quats, float* d_opacities,
-                   float* d_sh, hipStream_t stream) {
+static int render_bwd_impl(const sof_gaussians* g, const sof_camera* h_cams, const sof_camera* d_cams,
+                           int32_t n_cams, const sof_options* opts, const void* proj, size_t proj_bytes,
+                           const void* bins, size_t bins_bytes, const float* rgb, const float* normal,
+                           const float* aux, const float* d_rgb, const float* d_acc, const float* d_depth,
+                           const float* d_normal, const float* depth, const float* opacity, const float* d_opacity,
+                           const float* losses, const float* d_losses, void* grads, size_t grad_bytes,
+                           float* d_means, float* d_scales, float* d_quats, float* d_opacities, float* d_sh,
+                           hipStream_t stream) {
   int st = check_gauss(g, true);
   if (st) return st;
   RenderBwdArgs b;
@@ -292,6 +320,35 @@ int sof_render_bwd(const sof_gaussians* g, const sof_camera* h_cams, const sof_c
   pa.grads = (const float*)grads;
   pa.d_means = d_means; pa.d_scales = d_scales; pa.d_quats = d_quats; pa.d_opac = d_opacities; pa.d_sh = d_sh;
   return hip_status(launch_project_bwd(pa, stream));
+}
+
+int sof_render_bwd(const sof_gaussians* g, const sof_camera* h_cams, const sof_camera* d_cams, int32_t n_cams,
+                   const sof_options* opts, const void* proj, size_t proj_bytes, const void* bins, size_t bins_bytes,
+                   const float* rgb, const float* normal, const float* aux, const float* d_rgb, const float* d_acc,
+                   const float* d_depth, const float* d_normal, const float* depth, const float* opacity,
+                   const float* d_opacity, const float* losses, const float* d_losses, void* grads,
+                   size_t grad_bytes, float* d_means, float* d_scales, float* d_quats, float* d_opacities,
+                   float* d_sh, hipStream_t stream) {
+  return render_bwd_impl(g, h_cams, d_cams, n_cams, opts, proj, proj_bytes, bins, bins_bytes, rgb, normal, aux,
+                         d_rgb, d_acc, d_depth, d_normal, depth, opacity, d_opacity, losses, d_losses, grads,
+                         grad_bytes, d_means, d_scales, d_quats, d_opacities, d_sh, stream);
+}
+
+int sof_render_bwd_static(const sof_gaussians* g, const sof_camera* h_cams, const sof_camera* d_cams,
+                          int32_t n_cams, const sof_options* opts, const void* proj, size_t proj_bytes,
+                          const void* bins, size_t bins_bytes, const float* rgb, const float* normal,
+                          const float* aux, const float* d_rgb, const float* d_acc, const float* d_depth,
+                          const float* d_normal, const float* depth, const float* opacity, const float* d_opacity,
+                          const float* losses, const float* d_losses, float* d_means, float* d_scales,
+                          float* d_quats, float* d_opacities, float* d_sh, hipStream_t stream) {
+  if (!opts) return SOF_E_ARG;
+  if (opts->capacity > kStaticInstances) return SOF_E_SCRATCH;   // before any device call
+  void* ptr = nullptr;
+  const int st = static_scratch(&ptr);
+  if (st) return st;
+  return render_bwd_impl(g, h_cams, d_cams, n_cams, opts, proj, proj_bytes, bins, bins_bytes, rgb, normal, aux,
+                         d_rgb, d_acc, d_depth, d_normal, depth, opacity, d_opacity, losses, d_losses, ptr,
+                         sizeof(scratch), d_means, d_scales, d_quats, d_opacities, d_sh, stream);
 }
 
 }  // extern "C"

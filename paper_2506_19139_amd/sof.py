@@ -18,6 +18,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsof.so")
 
 SOF_OK, SOF_E_ARG, SOF_E_WORKSPACE, SOF_E_CAPACITY, SOF_E_HIP, SOF_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
+SOF_E_SCRATCH = -6
+STATIC_SCRATCH_INSTANCES = 1 << 20    # capacity limit of sof_render_bwd_static
 SOF_DEPTH_MEDIAN = 1 << 0
 SOF_DEPTH_GRAD_FULL = 1 << 1
 SOF_QUERY_KEYS = 1 << 2
@@ -73,6 +75,9 @@ _SIGS = {
     "sof_render_bwd": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, _P, _P, ctypes.c_size_t, _P, ctypes.c_size_t,
                                       _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P, _P,
                                       _P, _P, _P, _P]),
+    "sof_render_bwd_static": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, _P, _P, ctypes.c_size_t, _P,
+                                             ctypes.c_size_t, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
+                                             _P, _P, _P, _P, _P, _P]),
     "sof_query_workspace_size": (ctypes.c_int, [ctypes.c_int64, _P, ctypes.c_int32, _P, ctypes.c_int64,
                                                 ctypes.c_int64, _SZ, _SZ, _SZ]),
     "sof_opacity_query": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, _P, _P, ctypes.c_int64, ctypes.c_int64,
@@ -267,6 +272,20 @@ def render_bwd(g: Gaussians, cams: Cameras, opts: Options, proj, bins, rgb, norm
                                 grads.numel() if grads is not None else 0,
                                 _ptr(d_means), _ptr(d_scales), _ptr(d_quats), _ptr(d_opac), _ptr(d_sh), _stream()),
            "sof_render_bwd")
+
+
+def render_bwd_static(g: Gaussians, cams: Cameras, opts: Options, proj, bins, rgb, normal, aux, d_rgb, d_acc,
+                      d_depth, d_normal, d_means, d_scales, d_quats, d_opac, d_sh, depth=None, opacity=None,
+                      d_opacity=None, losses=None, d_losses=None):
+    """sof_render_bwd_static: the backward without a caller workspace (the library's static
+    per-device scratch holds the per-instance partials; opts.capacity <= 2^20)."""
+    gs, o = g.c_struct(), opts.c_struct()
+    _check(lib().sof_render_bwd_static(ctypes.byref(gs), cams.hp(), cams.dp(), len(cams), ctypes.byref(o),
+                                       _ptr(proj), proj.numel(), _ptr(bins), bins.numel(), _ptr(rgb), _ptr(normal),
+                                       _ptr(aux), _ptr(d_rgb), _ptr(d_acc), _ptr(d_depth), _ptr(d_normal),
+                                       _ptr(depth), _ptr(opacity), _ptr(d_opacity), _ptr(losses), _ptr(d_losses),
+                                       _ptr(d_means), _ptr(d_scales), _ptr(d_quats), _ptr(d_opac), _ptr(d_sh),
+                                       _stream()), "sof_render_bwd_static")
 
 
 def filter3d(g: Gaussians, cams: Cameras, k=0.2, near_plane=0.2):

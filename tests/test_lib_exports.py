@@ -102,3 +102,16 @@ def test_render_order_argument_checks():
     assert order(fake, 4, -1, fake, fake) == sof.SOF_E_ARG
     assert order(fake, 4, 8, None, fake) == sof.SOF_E_ARG
     assert order(fake, 4, 8, fake, None) == sof.SOF_E_ARG
+
+
+def test_static_backward_rejects_capacity_above_its_scratch():
+    """sof_render_bwd_static refuses a capacity above its fixed scratch before any device call."""
+    L = sof.lib()
+    o = sof.Options(tile=16, window=8, capacity=sof.STATIC_SCRATCH_INSTANCES + 1).c_struct()
+    args = [None] * 27
+    args[3], args[6], args[8] = 1, 0, 0                  # n_cams, proj_bytes, bins_bytes
+    plain = list(args)
+    args[4] = ctypes.byref(o)
+    assert L.sof_render_bwd_static(*args) == sof.SOF_E_SCRATCH
+    assert L.sof_render_bwd_static(*plain) == sof.SOF_E_ARG
+    assert b"static scratch" in L.sof_strerror(sof.SOF_E_SCRATCH)
