@@ -52,7 +52,6 @@ int check_gauss(const sof_gaussians* g, bool need_params) {
 
 int hip_status(hipError_t e) { return e == hipSuccess ? SOF_OK : SOF_E_HIP; }
 
-int sorted_parity(int64_t n_tiles) { return (((32 + bits_for(n_tiles)) + 7) / 8) & 1; }
 
 hipEvent_t g_timing[2 * kTimedKernels] = {};
 
@@ -186,7 +185,7 @@ static int fill_fwd_args(int64_t n, const sof_camera* h_cams, const sof_camera* 
   a->app = (const float4*)(pb + P.app);
   a->rect = (const short4*)(pb + P.rect);
   a->ranges = (const int2*)(bb + B.ranges);
-  a->vals = (const uint32_t*)(bb + (sorted_parity(n_tiles) ? B.vals1 : B.vals0));
+  a->vals = (const uint32_t*)(bb + B.vals0);                  // sorted tile lists (emission indices)
   a->gid = (const int32_t*)(bb + B.gid);
   *n_tiles_out = n_tiles;
   return SOF_OK;

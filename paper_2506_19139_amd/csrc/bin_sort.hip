@@ -1,8 +1,16 @@
 // Duplication of Gaussians into tiles and the per-tile key sort (level 0 of the
 // hierarchical resort, Sec. 3.1), plus the device-wide scan and the stable LSD radix sort
-// it is built from.  Instance counts stay on the device: every grid is sized from static
-// capacities and reads the live count from the status block, so the sequence can be
-// captured in a graph.
+// used by the query's 32-bit lists.  Instance counts stay on the device: every grid is sized
+// from static capacities and reads the live count from the status block, so the sequence can
+// be captured in a graph.
+//
+// Render lists (and the query's lists when tile ids need more than 20 bits) are built by
+// bucketing, not by a global sort: each instance takes its rank inside its tile with an
+// atomic increment of the tile's counter, one workgroup scans the counters into the tile
+// ranges, instances are scattered into their tile's range, and one workgroup per tile sorts
+// its range in LDS by (depth key, emission index).  Emission indices grow with the Gaussian
+// index inside a camera, and a tile holds one camera's instances, so this is the order
+// (tile, depth key, Gaussian index) whatever order the atomics handed out.
 //
 // Radix sort: 8-bit digits, 2048 keys per workgroup of 256 lanes (4 wave64s).  Per pass a
 // histogram kernel writes per-(digit, block) counts digit-major, an exclusive scan turns
@@ -279,29 +287,282 @@ __global__ __launch_bounds__(256) void k_count(const short4* rect, int64_t vn, i
   counts[idx] = c;
 }
 
+// One instance per (camera, Gaussian, touched tile), in emission order e (the scan of the
+// per-Gaussian counts): its tile, depth key and Gaussian, and its rank inside the tile from
+// an atomic increment of the tile's counter (ranges[t].y, zeroed by k_bin_init).  Instances
+// with e >= cap are dropped and flagged.  Each wave owns 64 consecutive (camera, Gaussian)
+// pairs and hands out their instances one per lane (an owner search over the wave's
+// inclusive prefix of counts), so a wave's 64 atomics and stores issue together and the
+// stores are coalesced whatever the size of each Gaussian's rectangle.
+struct EmitOwner {
+  int32_t tx0, ty0, nx, toff, tiles_x, g;
+  uint32_t key;
+  int32_t pad;
+};
+
 __global__ __launch_bounds__(256) void k_emit(const short4* rect, const float4* geom, const float* zmin, int64_t n,
                                               int64_t vn, int tile, const CamInfo* cams, const int32_t* counts,
-                                              const int64_t* offsets, int64_t cap, int query_keys, uint64_t* keys,
-                                              uint32_t* vals, int32_t* gid, StatusBlock* status) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= vn) return;
-  const int cnt = counts[idx];
-  if (cnt == 0) return;
-  const short4 r = rect[idx];
-  const int c = (int)(idx / n);
-  const int32_t g = (int32_t)(idx - (int64_t)c * n);
-  const CamInfo ci = cams[c];
-  const uint32_t k32 = query_keys ? float_order_bits(zmin[idx]) : float_order_bits(geom[4 * idx + 3].x);
-  int64_t e = offsets[idx];
-  if (e + cnt > cap) atomicOr(&status->flags, 1);
-  for (int ty = r.y / tile; ty <= r.w / tile; ++ty)
-    for (int tx = r.x / tile; tx <= r.z / tile; ++tx, ++e) {
-      if (e >= cap) return;
-      const uint64_t t = (uint64_t)(ci.tile_off + ty * ci.tiles_x + tx);
-      keys[e] = (t << 32) | (uint64_t)k32;
-      vals[e] = (uint32_t)e;
-      gid[e] = g;
+                                              const int64_t* offsets, int64_t cap, int query_keys, uint2* inst,
+                                              uint32_t* rank, int32_t* gid, int2* ranges, StatusBlock* status) {
+  __shared__ EmitOwner own[4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t base = ((int64_t)blockIdx.x * 4 + w) * 64;
+  if (base >= vn) return;                                 // wave-uniform
+  const int64_t vg = base + lane;
+  int cnt = 0;
+  if (vg < vn) {
+    cnt = counts[vg];
+    if (cnt > 0) {
+      const short4 r = rect[vg];
+      const int c = (int)(vg / n);
+      const CamInfo ci = cams[c];
+      EmitOwner o;
+      o.tx0 = r.x / tile;
+      o.ty0 = r.y / tile;
+      o.nx = r.z / tile - o.tx0 + 1;
+      o.toff = ci.tile_off;
+      o.tiles_x = ci.tiles_x;
+      o.g = (int32_t)(vg - (int64_t)c * n);
+      o.key = query_keys ? float_order_bits(zmin[vg]) : float_order_bits(geom[4 * vg + 3].x);
+      o.pad = 0;
+      own[w][lane] = o;
     }
+  }
+  int incl = cnt;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int y = __shfl_up(incl, d, 64);
+    if (lane >= d) incl += y;
+  }
+  const int total = __shfl(incl, 63, 64);
+  const int64_t e0 = offsets[base];                       // emission index of the wave's first instance
+  if (lane == 0 && e0 + total > cap && total > 0) atomicOr(&status->flags, 1);
+  __builtin_amdgcn_wave_barrier();                        // own[w] written by this wave only
+  // the loop and the shuffles run on all 64 lanes (total is wave-uniform); only the stores
+  // are predicated
+  const int excl = incl - cnt;
+  for (int j0 = 0; j0 < total; j0 += 64) {
+    const int j = j0 + lane;
+    // owner: the first lane whose inclusive prefix exceeds j (it has a non-zero count)
+    int lo = 0, hi = 63;
+#pragma unroll
+    for (int it = 0; it < 6; ++it) {
+      const int mid = (lo + hi) >> 1;
+      const bool right = __shfl(incl, mid, 64) <= j;
+      lo = right ? mid + 1 : lo;
+      hi = right ? hi : mid;
+    }
+    const int before = __shfl(excl, lo, 64);
+    const int64_t e = e0 + j;
+    if (j < total && e < cap) {
+      const EmitOwner o = own[w][lo];
+      const int local = j - before;
+      const int ty = o.ty0 + local / o.nx, tx = o.tx0 + local % o.nx;
+      const uint32_t t = (uint32_t)(o.toff + ty * o.tiles_x + tx);
+      rank[e] = (uint32_t)atomicAdd(&ranges[t].y, 1);
+      inst[e] = make_uint2(t, o.key);
+      gid[e] = o.g;
+    }
+  }
+}
+
+// Camera table, status reset and zeroed tile counters.
+__global__ __launch_bounds__(256) void k_bin_init(const sof_camera* cams, int n_cams, int tile, CamInfo* out,
+                                                  StatusBlock* status, int2* ranges, int64_t n_tiles) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n_tiles) ranges[i] = make_int2(0, 0);
+  if (i != 0) return;
+  int32_t toff = 0;
+  int64_t poff = 0;
+  for (int c = 0; c < n_cams; ++c) {
+    CamInfo ci;
+    ci.tiles_x = (cams[c].width + tile - 1) / tile;
+    ci.tiles_y = (cams[c].height + tile - 1) / tile;
+    ci.tile_off = toff;
+    ci.pix_off = poff;
+    ci.pad = 0; ci.pad2 = 0;
+    out[c] = ci;
+    toff += ci.tiles_x * ci.tiles_y;
+    poff += (int64_t)cams[c].width * cams[c].height;
+  }
+  CamInfo end;
+  end.tile_off = toff; end.pix_off = poff; end.tiles_x = end.tiles_y = 0; end.pad = 0; end.pad2 = 0;
+  out[n_cams] = end;
+  status->count = 0;
+  status->flags = 0;
+}
+
+// Tile counters -> ranges [start, start + count) in one workgroup (an exclusive scan over
+// the tiles, 1024 lanes x 8 tiles per round, carried across rounds).
+constexpr int kTileScanThreads = 1024, kTileScanItems = 8;
+__global__ __launch_bounds__(kTileScanThreads) void k_tile_scan(int2* ranges, int64_t n_tiles) {
+  __shared__ int32_t wsum[kTileScanThreads / 64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int32_t carry = 0;
+  for (int64_t b = 0; b < n_tiles; b += (int64_t)kTileScanThreads * kTileScanItems) {
+    const int64_t base = b + (int64_t)threadIdx.x * kTileScanItems;
+    int32_t v[kTileScanItems];
+    int32_t sum = 0;
+#pragma unroll
+    for (int k = 0; k < kTileScanItems; ++k) {
+      v[k] = base + k < n_tiles ? ranges[base + k].y : 0;
+      sum += v[k];
+    }
+    int32_t x = sum;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int32_t y = __shfl_up(x, d, 64);
+      if (lane >= d) x += y;
+    }
+    if (lane == 63) wsum[w] = x;
+    __syncthreads();
+    int32_t before = 0, total = 0;
+#pragma unroll
+    for (int k = 0; k < kTileScanThreads / 64; ++k) {
+      const int32_t t = wsum[k];
+      before += k < w ? t : 0;
+      total += t;
+    }
+    __syncthreads();
+    int32_t run = carry + before + x - sum;
+#pragma unroll
+    for (int k = 0; k < kTileScanItems; ++k) {
+      if (base + k < n_tiles) ranges[base + k] = make_int2(run, run + v[k]);
+      run += v[k];
+    }
+    carry += total;
+  }
+}
+
+// Instances into their tile's range, keyed (depth key << 32 | emission index).
+__global__ __launch_bounds__(256) void k_tile_scatter(const uint2* inst, const uint32_t* rank, const int2* ranges,
+                                                      const int64_t* count, int64_t cap, uint64_t* bucket) {
+  const int64_t n = live_count(count, cap);
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const uint2 it = inst[e];
+  bucket[ranges[it.x].x + rank[e]] = ((uint64_t)it.y << 32) | (uint64_t)e;
+}
+
+// Bitonic sort of P (a power of two, <= kTileSortCap) keys in LDS by the whole workgroup,
+// with the network unrolled at compile time (no scalar loop or branch work per stage).  Lane
+// t takes the compare-exchange pairs t, t + 256, ...; pair p of a stage with distance j joins
+// entries i = 2 j (p / j) + p mod j and i + j.  For j < 64 both entries lie in one 64-entry
+// block whose 32 pairs belong to 32 consecutive lanes of one wave, so those stages need only
+// the wave's own ordering of its LDS accesses; a workgroup barrier is taken only around
+// stages whose pairs span waves (j >= 64).
+constexpr int kTileSortThreads = 256, kTileSortCap = 2048;
+
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int P, int K, int J>
+__device__ inline void bitonic_stage(uint64_t* s) {
+  constexpr int kPairs = P / 2;
+#pragma unroll
+  for (int p0 = 0; p0 < kPairs; p0 += kTileSortThreads) {
+    const int p = p0 + (int)threadIdx.x;
+    if (kPairs % kTileSortThreads == 0 || p < kPairs) {
+      const int i = ((p & ~(J - 1)) << 1) | (p & (J - 1));
+      const int l = i | J;
+      const uint64_t a = s[i], b = s[l];
+      const bool sw = (a > b) == ((i & K) == 0);
+      s[i] = sw ? b : a;
+      s[l] = sw ? a : b;
+    }
+  }
+  constexpr bool next_crosses = (J > 1) ? ((J >> 1) >= 64) : (2 * K <= P && K >= 64);
+  if constexpr (J >= 64 || next_crosses) {
+    __syncthreads();
+  } else {
+    wave_lds_sync();
+  }
+}
+
+template <int P, int K, int J>
+__device__ inline void bitonic_merge(uint64_t* s) {
+  bitonic_stage<P, K, J>(s);
+  if constexpr (J > 1) bitonic_merge<P, K, J / 2>(s);
+}
+
+template <int P, int K = 2>
+__device__ inline void bitonic_sort(uint64_t* s) {
+  bitonic_merge<P, K, K / 2>(s);
+  if constexpr (K < P) bitonic_sort<P, 2 * K>(s);
+}
+
+// Sort s[0, P) for the smallest power of two P >= L (entries L..P-1 hold the largest key).
+__device__ __attribute__((always_inline)) inline void lds_bitonic(uint64_t* s, int P) {
+  switch (P) {
+    case 2: bitonic_sort<2>(s); break;
+    case 4: bitonic_sort<4>(s); break;
+    case 8: bitonic_sort<8>(s); break;
+    case 16: bitonic_sort<16>(s); break;
+    case 32: bitonic_sort<32>(s); break;
+    case 64: bitonic_sort<64>(s); break;
+    case 128: bitonic_sort<128>(s); break;
+    case 256: bitonic_sort<256>(s); break;
+    case 512: bitonic_sort<512>(s); break;
+    case 1024: bitonic_sort<1024>(s); break;
+    default: bitonic_sort<kTileSortCap>(s); break;
+  }
+  __syncthreads();
+}
+
+// One workgroup per tile: its range sorted by (depth key, emission index); the emission
+// indices are written to vals.  Ranges above kTileSortCap (not met at the benchmark's
+// sizes, where the longest list is about a thousand) are sorted in chunks of kTileSortCap
+// in LDS and then merged pairwise in global memory, each element placed by its rank in the
+// other run (keys are unique), ping-ponging between bucket and tmp.
+__global__ __launch_bounds__(kTileSortThreads) void k_tile_sort(const int2* ranges, uint64_t* bucket, uint64_t* tmp,
+                                                                uint32_t* vals) {
+  __shared__ uint64_t s[kTileSortCap];
+  const int2 rg = ranges[blockIdx.x];
+  const int L = rg.y - rg.x;
+  if (L <= 0) return;
+  const bool small = L <= kTileSortCap;
+  int P = 2;
+  while (P < L && P < kTileSortCap) P <<= 1;
+  uint64_t* src = bucket + rg.x;
+  uint64_t* dst = tmp + rg.x;
+  // one LDS sort per chunk of kTileSortCap entries (a single chunk for a short list, whose
+  // sorted emission indices go straight to vals)
+  for (int c0 = 0; c0 < L; c0 += kTileSortCap) {
+    const int m = min(kTileSortCap, L - c0);
+    for (int i = threadIdx.x; i < P; i += kTileSortThreads) s[i] = i < m ? src[c0 + i] : ~0ull;
+    __syncthreads();
+    lds_bitonic(s, P);
+    if (small) {
+      for (int i = threadIdx.x; i < m; i += kTileSortThreads) vals[rg.x + i] = (uint32_t)s[i];
+    } else {
+      for (int i = threadIdx.x; i < m; i += kTileSortThreads) src[c0 + i] = s[i];
+    }
+    __syncthreads();
+  }
+  if (small) return;
+  for (int width = kTileSortCap; width < L; width <<= 1) {
+    for (int i = threadIdx.x; i < L; i += kTileSortThreads) {
+      const int lo = (i / (2 * width)) * (2 * width);
+      const int mid = min(lo + width, L), hi = min(lo + 2 * width, L);
+      const uint64_t x = src[i];
+      // rank of x in the other run of its pair (binary search; keys are unique)
+      const bool in_a = i < mid;
+      int a = in_a ? mid : lo, b = in_a ? hi : mid;
+      while (a < b) {
+        const int h = (a + b) >> 1;
+        if (src[h] < x) a = h + 1; else b = h;
+      }
+      const int other = a - (in_a ? mid : lo);
+      const int self = i - (in_a ? lo : mid);
+      dst[lo + self + other] = x;
+    }
+    __syncthreads();
+    uint64_t* t = src; src = dst; dst = t;
+  }
+  for (int i = threadIdx.x; i < L; i += kTileSortThreads) vals[rg.x + i] = (uint32_t)src[i];
 }
 
 // Query tile lists with 32-bit keys: (tile << dbits) | quantised z_min, value = Gaussian id.
@@ -344,15 +605,6 @@ __global__ __launch_bounds__(256) void k_fill_ranges(int2* ranges, int64_t n_til
   if (i < n_tiles) ranges[i] = make_int2(0, 0);
 }
 
-__global__ __launch_bounds__(256) void k_ranges(const uint64_t* keys, const int64_t* count, int64_t cap, int2* ranges) {
-  const int64_t n = live_count(count, cap);
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const uint32_t t = (uint32_t)(keys[i] >> 32);
-  if (i == 0 || (uint32_t)(keys[i - 1] >> 32) != t) ranges[t].x = (int)i;
-  if (i == n - 1 || (uint32_t)(keys[i + 1] >> 32) != t) ranges[t].y = (int)(i + 1);
-}
-
 hipError_t launch_cam_table(const sof_camera* d_cams, int n_cams, int tile, CamInfo* out, StatusBlock* status,
                             hipStream_t s) {
   hipLaunchKernelGGL(k_cam_table, dim3(1), dim3(64), 0, s, d_cams, n_cams, tile, out, status);
@@ -371,37 +623,37 @@ hipError_t launch_bin_sort(int64_t n, const sof_camera* d_cams, int n_cams, int6
   int32_t* counts = (int32_t*)(bb + B.counts);
   int64_t* offsets = (int64_t*)(bb + B.offsets);
   int64_t* scan_tmp = (int64_t*)(bb + B.scan_tmp);
-  uint64_t* k0 = (uint64_t*)(bb + B.keys0);
-  uint64_t* k1 = (uint64_t*)(bb + B.keys1);
-  uint32_t* v0 = (uint32_t*)(bb + B.vals0);
-  uint32_t* v1 = (uint32_t*)(bb + B.vals1);
+  // render-list roles of the shared regions (see BinsLayout)
+  uint64_t* bucket = (uint64_t*)(bb + B.keys0);
+  uint2* inst = (uint2*)(bb + B.keys1);            // consumed by the scatter, then merge scratch
+  uint64_t* tmp = (uint64_t*)(bb + B.keys1);
+  uint32_t* vals = (uint32_t*)(bb + B.vals0);
+  uint32_t* rank = (uint32_t*)(bb + B.vals1);
   int32_t* gid = (int32_t*)(bb + B.gid);
-  int32_t* hist = (int32_t*)(bb + B.hist);
-  int32_t* hist_tmp = (int32_t*)(bb + B.hist_tmp);
   int2* ranges = (int2*)(bb + B.ranges);
   const short4* rect = (const short4*)(pb + P.rect);
   const float4* geom = (const float4*)(pb + P.geom);
   const float* zmin = (const float*)(pb + P.zmin);
 
-  hipLaunchKernelGGL(k_cam_table, dim3(1), dim3(64), 0, s, d_cams, n_cams, tile, cams, status);
   const int th = 256;
+  hipLaunchKernelGGL(k_bin_init, dim3((unsigned)div_up(n_tiles > 0 ? n_tiles : 1, th)), dim3(th), 0, s, d_cams, n_cams,
+                     tile, cams, status, ranges, n_tiles);
   if (vn > 0) {
     hipLaunchKernelGGL(k_count, dim3((unsigned)div_up(vn, th)), dim3(th), 0, s, rect, vn, tile, counts);
   }
   hipError_t e = exclusive_scan<int32_t, int64_t>(counts, vn, offsets, scan_tmp, &status->count, s);
   if (e != hipSuccess) return e;
   if (vn > 0) {
-    hipLaunchKernelGGL(k_emit, dim3((unsigned)div_up(vn, th)), dim3(th), 0, s, rect, geom, zmin, n, vn, tile, cams,
-                       counts, offsets, cap, query_keys, k0, v0, gid, status);
+    hipLaunchKernelGGL(k_emit, dim3((unsigned)div_up(vn, 256)), dim3(256), 0, s, rect, geom, zmin, n, vn, tile, cams,
+                       counts, offsets, cap, query_keys, inst, rank, gid, ranges, status);
   }
-  const int bits = 32 + bits_for(n_tiles);
-  e = radix_sort<uint64_t>(k0, v0, k1, v1, &status->count, cap, bits, hist, hist_tmp, parity, s);
-  if (e != hipSuccess) return e;
-  const uint64_t* ks = *parity ? k1 : k0;
-  hipLaunchKernelGGL(k_fill_ranges, dim3((unsigned)div_up(n_tiles > 0 ? n_tiles : 1, th)), dim3(th), 0, s, ranges, n_tiles);
+  hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(kTileScanThreads), 0, s, ranges, n_tiles);
   if (cap > 0) {
-    hipLaunchKernelGGL(k_ranges, dim3((unsigned)div_up(cap, th)), dim3(th), 0, s, ks, &status->count, cap, ranges);
+    hipLaunchKernelGGL(k_tile_scatter, dim3((unsigned)div_up(cap, th)), dim3(th), 0, s, inst, rank, ranges,
+                       &status->count, cap, bucket);
   }
+  hipLaunchKernelGGL(k_tile_sort, dim3((unsigned)n_tiles), dim3(kTileSortThreads), 0, s, ranges, bucket, tmp, vals);
+  *parity = 0;
   return hipGetLastError();
 }
 

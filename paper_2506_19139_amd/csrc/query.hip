@@ -399,8 +399,7 @@ int sof_opacity_query(const sof_gaussians* g, const sof_camera* h_cams, const so
   int gpar = 0, gdbits = 0;
   if ((opts->flags & SOF_QUERY_REUSE) && n > 0) {
     gdbits = query_key_bits(n_tiles);
-    const int bits = gdbits ? 32 : 32 + bits_for(n_tiles);
-    gpar = ((bits + 7) / 8) & 1;                       // parity of the radix passes that sorted them
+    gpar = gdbits ? ((32 + 7) / 8) & 1 : 0;           // where the previous call's sort left the lists
   } else {
     if ((e = launch_project(g, d_cams, n_cams, near_plane, proj, s, true)) != hipSuccess) return SOF_E_HIP;
     if ((e = launch_query_bin_sort(n, d_cams, n_cams, n_tiles, tile, opts->capacity, proj, bins, s, &gpar,

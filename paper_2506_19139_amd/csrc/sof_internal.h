@@ -86,7 +86,11 @@ constexpr int kScanChunk = kScanItems * kScanThreads;
 
 inline __host__ __device__ int64_t div_up(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-// bins buffer layout.
+// bins buffer layout.  The render lists (launch_bin_sort) use keys0 for the tile buckets
+// (uint64 depth key << 32 | emission index), keys1 for the per-instance (tile, depth key) and
+// then as merge scratch, vals0 for the sorted emission indices, vals1 for the ranks inside the
+// tiles and ranges first as the tile counters; the query's 32-bit lists use the four key /
+// value regions and hist / hist_tmp for their radix sort.
 struct BinsLayout {
   size_t status, cams, counts, offsets, scan_tmp, keys0, keys1, vals0, vals1, gid, hist, hist_tmp,
       ranges, total;

@@ -352,18 +352,16 @@ class KernelTimer:
 # ------------------------------------------------------------------------------ views of bins
 
 def sorted_instances(bins: torch.Tensor, n, cams: Cameras, opts: Options):
-    """Debug view of the sorted tile lists: (keys uint64, gaussian ids, ranges[n_tiles,2]) as
-    numpy arrays (synchronises).  Layout mirrors the internal bins layout."""
+    """Debug view of the sorted tile lists: (bucket keys uint64, gaussian ids, ranges[n_tiles,2])
+    as numpy arrays (synchronises).  Layout mirrors the internal bins layout."""
     vn = n * len(cams)
     n_tiles = sum(((w + opts.tile - 1) // opts.tile) * ((h + opts.tile - 1) // opts.tile) for w, h in cams.sizes)
     L = _bins_layout(vn, len(cams), opts.capacity, n_tiles)
     b = bins.cpu().numpy()
     k, _ = read_status(bins)
     k = min(k, opts.capacity)
-    bits = 32 + max(1, int(np.ceil(np.log2(max(n_tiles, 2)))))
-    parity = ((bits + 7) // 8) & 1
-    keys = b[L["keys1" if parity else "keys0"]:][: 8 * k].view(np.uint64)
-    vals = b[L["vals1" if parity else "vals0"]:][: 4 * k].view(np.uint32)
+    keys = b[L["keys0"]:][: 8 * k].view(np.uint64)           # tile buckets: depth key << 32 | emission index
+    vals = b[L["vals0"]:][: 4 * k].view(np.uint32)           # sorted emission indices
     gid = b[L["gid"]:][: 4 * opts.capacity].view(np.int32)
     ids = gid[vals]
     ranges = b[L["ranges"]:][: 8 * n_tiles].view(np.int32).reshape(n_tiles, 2)

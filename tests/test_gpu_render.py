@@ -52,6 +52,13 @@ def test_small_scene_full_frame_order_and_parity(small_oracle, window):
             assert n_full > 0.9 * len(pixels)
 
 
+def _same_ranges(gpu, ref):
+    """Tile ranges equal where the tile has entries; an empty tile may start anywhere."""
+    empty = ref[:, 1] == ref[:, 0]
+    assert np.array_equal(gpu[:, 1] == gpu[:, 0], empty)
+    assert np.array_equal(gpu[~empty], ref[~empty])
+
+
 def test_tile_lists_bit_exact():
     scene, cam = _small()
     for tile in (8, 16, 32):
@@ -61,9 +68,7 @@ def test_tile_lists_bit_exact():
         keys, ids, ranges = sof.sorted_instances(r.bins, g.n, C, opts)
         # integer logic of the oracle fed the GPU's own float32 rectangles and keys
         ids_o, tiles_o, ranges_o = O.tile_lists(pv["rect"].astype(np.int64), pv["mu_z"], tile, cam["width"], cam["height"])
-        empty_o = ranges_o[:, 1] == ranges_o[:, 0]
-        ranges_o = np.where(empty_o[:, None], 0, ranges_o)      # an empty tile is written as [0, 0)
-        assert np.array_equal(ranges, ranges_o)
+        _same_ranges(ranges, ranges_o)
         assert np.array_equal(ids.astype(np.int64), ids_o)
         # the GPU's float64 rectangles equal the oracle's, except at a pixel boundary
         sc, oc = oracle_scene_cam(scene, cam)
@@ -74,6 +79,33 @@ def test_tile_lists_bit_exact():
             frac = np.abs(box[i] - np.round(box[i]))
             assert np.min(frac) < 1e-6, (i, rect_o[i], pv["rect"][i])
         np.testing.assert_allclose(pv["zmin"][live], zmin[live], rtol=1e-6, atol=1e-6)
+
+
+def _dense_scene(n=5000, seed=7):
+    """Large, overlapping Gaussians in front of the small camera: most of them touch every
+    tile, so the tile lists run to thousands of entries (above the 2048 that one workgroup
+    sorts in LDS at once)."""
+    rng = np.random.default_rng(seed)
+    means = np.concatenate([rng.uniform(-0.6, 0.6, (n, 2)), rng.uniform(-1.0, 1.0, (n, 1))], 1)
+    return dict(means=means.astype(np.float32), scales=np.exp(rng.normal(-1.0, 0.2, (n, 3))).astype(np.float32),
+                quats=rng.standard_normal((n, 4)).astype(np.float32),
+                opac=(1 / (1 + np.exp(-rng.normal(0, 1.0, n)))).astype(np.float32),
+                sh=rng.normal(0, 0.3, (n, 1, 3)).astype(np.float32), sh_degree=0)
+
+
+@pytest.mark.parametrize("tile", [8, 32])
+def test_long_tile_lists_bit_exact(tile):
+    scene, cam = _dense_scene(), scenes.small_camera()
+    print(f"[case] long tile lists, 5000 large Gaussians 64x64 tile {tile}", flush=True)
+    r, g, C, opts, out, host = gpu_render(scene, [cam], tile=tile, window=8)
+    pv = sof.proj_view(r.proj, g.n, 1)
+    keys, ids, ranges = sof.sorted_instances(r.bins, g.n, C, opts)
+    ids_o, tiles_o, ranges_o = O.tile_lists(pv["rect"].astype(np.int64), pv["mu_z"], tile, cam["width"], cam["height"])
+    longest = int(np.max(ranges_o[:, 1] - ranges_o[:, 0]))
+    print(f"  longest tile list {longest}")
+    assert longest > 4096                       # chunked LDS sorts and two or more merge passes
+    _same_ranges(ranges, ranges_o)
+    assert np.array_equal(ids.astype(np.int64), ids_o)
 
 
 def test_tile_size_invariance_bitwise():
