@@ -171,15 +171,20 @@ int sof_bin_sort(int64_t n, const sof_camera* h_cams, const sof_camera* d_cams, 
  *   aux    [6,H,W] float32 bits T_end, n_emitted (int32), k (int32 Gaussian index or -1),
  *                               T_k -- needed by sof_render_bwd -- then two int32 work
  *                               counters: list entries tested and candidates found.
- *   losses [4,H,W]              the per-pixel distortion and extent losses of Sec. 3.3
- *                               (App. C.1, C.2), then two moments sof_render_bwd needs.  With
+ *   losses [6,H,W]              the per-pixel distortion and extent losses of Sec. 3.3
+ *                               (App. C.1, C.2), then two moments sof_render_bwd needs, then
+ *                               two channels sof_render_opacity reads (below).  With
  *                               d = NDC(t*) = f (t* - n) / ((f - n) t*), n = 0.2, f = 100,
  *                               over the blended Gaussians: distortion = sum_ij w_i w_j
  *                               (d_i - d_j)^2 = 2 A M with A = sum w, mean mu = sum w d / A
  *                               and M = sum w (d - mu)^2 (channels 2, 3, accumulated one
  *                               Gaussian at a time); extent = f n / (f - n) sum w 2 A_i
- *                               sqrt(B_i^2 - 4 A_i (C_i - E_i^2)) / B_i^2.  NULL: not computed
- *                               (a kernel without this work runs).
+ *                               sqrt(B_i^2 - 4 A_i (C_i - E_i^2)) / B_i^2.  Channel 4 is
+ *                               prod_{i >= k} (1 - alpha_i(x)) over the blended Gaussians from
+ *                               the crossing Gaussian k on, each at x = o + t_r d (t_r the depth
+ *                               output; alpha as in sof_render_opacity), channel 5 the position
+ *                               of k in the blend order (int32, -1 without a crossing).  NULL:
+ *                               not computed (a kernel without this work runs).
  */
 int sof_render_fwd(int64_t n, const sof_camera* h_cams, const sof_camera* d_cams, int32_t n_cams,
                    const sof_options* opts, const void* proj, size_t proj_bytes, const void* bins,
@@ -221,13 +226,17 @@ int sof_render_order(int64_t n, const sof_camera* h_cams, const sof_camera* d_ca
  * x = o + t_r d, t_r the depth the forward wrote, over the Gaussians the pixel blended, each
  * with alpha = min(0.99, o_i G_i(min(t*_i, t_r))) and counted when alpha >= 1/255 and the
  * evaluated point lies beyond the near plane (Eq. (12)); 0 where there is no crossing.
- * The pass replays the forward's per-pixel order up to its blend count.  Overwrites
- * opacity [sum of W H].  The L_opa loss |O_N - 0.5|^2 is the caller's to form.
+ * The pass replays the forward's per-pixel order.  With `losses` (the forward's [6,H,W]
+ * losses output, or NULL) it uses the paper's split O_N = O_k + T_k sum_{i >= k} alpha_i
+ * prod_{k <= j < i} (1 - alpha_j): the forward accumulated the part from the crossing
+ * Gaussian k on, and the replay stops in front of k; with NULL it replays every blended
+ * Gaussian.  Both give O_N up to float rounding.  Overwrites opacity [sum of W H].  The
+ * L_opa loss |O_N - 0.5|^2 is the caller's to form.
  */
 int sof_render_opacity(int64_t n, const sof_camera* h_cams, const sof_camera* d_cams, int32_t n_cams,
                        const sof_options* opts, const void* proj, size_t proj_bytes, const void* bins,
-                       size_t bins_bytes, const float* depth, const float* aux, float* opacity,
-                       hipStream_t stream);
+                       size_t bins_bytes, const float* depth, const float* aux, const float* losses,
+                       float* opacity, hipStream_t stream);
 
 /*
  * sof_render_bwd -- adjoint of sof_render_fwd, sof_render_opacity and sof_project.

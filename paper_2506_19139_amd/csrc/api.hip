@@ -253,7 +253,8 @@ int sof_filter3d_bwd(const sof_gaussians* g, const float* var, const float* d_sc
 
 int sof_render_opacity(int64_t n, const sof_camera* h_cams, const sof_camera* d_cams, int32_t n_cams,
                        const sof_options* opts, const void* proj, size_t proj_bytes, const void* bins,
-                       size_t bins_bytes, const float* depth, const float* aux, float* opacity, hipStream_t stream) {
+                       size_t bins_bytes, const float* depth, const float* aux, const float* losses, float* opacity,
+                       hipStream_t stream) {
   RenderOpaArgs a;
   int64_t n_tiles = 0;
   int st = fill_fwd_args(n, h_cams, d_cams, n_cams, opts, proj, proj_bytes, bins, bins_bytes, &a.f, &n_tiles);
@@ -261,6 +262,7 @@ int sof_render_opacity(int64_t n, const sof_camera* h_cams, const sof_camera* d_
   if (!depth || !aux || !opacity) return SOF_E_ARG;
   a.f.depth = (float*)depth;
   a.f.aux = (float*)aux;
+  a.tail = losses;
   a.opa = opacity;
   if (trace_enabled())
     fprintf(stderr, "[sof] render_opacity tiles=%lld tile=%d window=%d\n", (long long)n_tiles, opts->tile, opts->window);

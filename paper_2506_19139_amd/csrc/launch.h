@@ -83,6 +83,7 @@ struct RenderBwdArgs {
 
 struct RenderOpaArgs {
   RenderFwdArgs f;          // f.depth and f.aux are the forward's outputs (read)
+  const float* tail;        // the forward's loss outputs (opacity tail, position of k), or null
   float* opa;
 };
 

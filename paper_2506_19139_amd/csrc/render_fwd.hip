@@ -14,9 +14,23 @@ struct PixFwd {
   float T, r, g, b, nx, ny, nz, Tk;
   float A, mu, M, E;         // losses only: sum w, weighted mean and central second moment of
                              // d = NDC(t*) (updated one Gaussian at a time), sum w extent
-  int n_emit, k, walked, cands;
+  float sr, Pt;              // losses only: view z of the rendered depth on this ray and the
+                             // product of (1 - alpha_i(x)) from the crossing Gaussian on
+  int n_emit, k, kpos, walked, cands;   // kpos: position of k in the blend order
   bool done;
 };
+
+// Output depth of the crossing Gaussian (record r3, quadric terms q at this pixel, T_k):
+// the exact depth of the 0.5 level set (Sec. 3.2, App. A.3), or t*_k with SOF_DEPTH_MEDIAN.
+__device__ inline float crossing_depth(const float4& r3, const Quad& q, float Tk, float dn, uint32_t flags) {
+  const float sstar = r3.x * (1.f + q.b) / q.den;
+  if (flags & SOF_DEPTH_MEDIAN) return dn * sstar;
+  const float x = fmaxf(q.num / q.den, 0.f);                 // K q*
+  const float g = (Tk - 0.5f) / (Tk * r3.y);
+  const float L = fmaxf(2.f * (-x * kLn2 - logf(g)), 0.f);  // 2 ln(G*/g)
+  const float A = r3.w * q.den;                              // d^T P d, d = (x_n, y_n, 1)
+  return dn * (sstar - sqrtf(L / A));
+}
 
 // Returns the blend weight (0 when the Gaussian was not blended).
 __device__ inline float blend(PixFwd& p, float alpha, uint32_t gid, const float4* app, int64_t cam_base) {
@@ -36,6 +50,7 @@ __device__ inline float blend(PixFwd& p, float alpha, uint32_t gid, const float4
   p.nz = fmaf(w, nn.z, p.nz);
   if (p.k < 0 && test_T <= 0.5f) {
     p.k = (int)gid;
+    p.kpos = p.n_emit;
     p.Tk = p.T;
   }
   p.T = test_T;
@@ -47,8 +62,14 @@ __device__ inline float blend(PixFwd& p, float alpha, uint32_t gid, const float4
 // depth d = NDC(t*) and the extent e = eps / t*^2 of its 1/255 contour along the ray,
 // eps = sqrt((E^2 - q*) / A) on the unit ray; in the stored view-z units
 // e = sqrt((E^2 - q*) / A_s) / (|d~| s*^2) with A_s = d~^T P d~.
+//
+// The same pass accumulates the tail of the opacity field at the rendered depth (Sec. 3.3,
+// direct opacity-field supervision): once the crossing Gaussian k is blended, its depth is
+// known, and from k on every blended Gaussian's alpha at x = o + t_r d (t_eval = min(t*,
+// t_r), the 1/255 and near-plane rules of Eq. (12)) multiplies Pt = prod_{i >= k} (1 -
+// alpha_i(x)); the second pass then needs only the Gaussians in front of k.
 __device__ inline void loss_terms(PixFwd& p, float w, float sstar, uint32_t gid, const float4* geom, int64_t cam_base,
-                                  int px, int py, float dn) {
+                                  int px, int py, float dn, bool crossed_here, uint32_t flags, float near_plane) {
   const int64_t vg = cam_base + gid;
   const float4 r0 = geom[4 * vg], r1 = geom[4 * vg + 1], r2 = geom[4 * vg + 2], r3 = geom[4 * vg + 3];
   const float2 d2 = pixel_offset(r0, px, py);
@@ -56,6 +77,19 @@ __device__ inline void loss_terms(PixFwd& p, float w, float sstar, uint32_t gid,
   // hardware reciprocals (1 ulp): these values only enter the losses, never a decision
   // E^2 - q* = 2 ln 2 (log2(255 o) - x*): the record keeps log2(255 o) (the 1/255 cut)
   const float xs = fmaxf(q.num * __builtin_amdgcn_rcpf(q.den), 0.f);
+  if (crossed_here) p.sr = crossing_depth(r3, q, p.Tk, dn, flags) / dn;   // as the stored depth / |d~|
+  if (p.k >= 0) {
+    // alpha at x: at the peak (the blend alpha) when it lies in front of x, else at x
+    const float araw = r3.y * __builtin_amdgcn_exp2f(-xs);
+    float ax = fminf(kAlphaMax, araw);
+    bool keep = true;
+    if (sstar > p.sr) {
+      const float ds = p.sr - sstar;
+      ax = fminf(kAlphaMax, araw * __builtin_amdgcn_exp2f(-kHalfLog2e * (r3.w * q.den) * ds * ds));
+      keep = ax >= kAlphaMin && p.sr > near_plane;
+    }
+    p.Pt = keep ? p.Pt * (1.f - ax) : p.Pt;
+  }
   const float u = (2.f * kLn2) * fmaxf(r3.z - xs, 0.f);
   const float t = dn * sstar, it = __builtin_amdgcn_rcpf(t);
   const float e = sqrtf(u * __builtin_amdgcn_rcpf(r3.w * q.den)) * it * __builtin_amdgcn_rcpf(sstar);
@@ -83,16 +117,7 @@ __device__ inline void write_pixel(const RenderFwdArgs& a, const PixFwd& p, cons
     const float4 r0 = a.geom[4 * vg], r1 = a.geom[4 * vg + 1], r2 = a.geom[4 * vg + 2], r3 = a.geom[4 * vg + 3];
     const float2 d = pixel_offset(r0, px, py);
     const Quad q = quad_terms(r1.x, r1.y, r1.z, r1.w, r2.x, r2.y, r2.z, r2.w, d.x, d.y);
-    const float sstar = r3.x * (1.f + q.b) / q.den;
-    if (a.flags & SOF_DEPTH_MEDIAN) {
-      depth = dn * sstar;
-    } else {
-      const float x = fmaxf(q.num / q.den, 0.f);                 // K q*
-      const float g = (p.Tk - 0.5f) / (p.Tk * r3.y);
-      const float L = fmaxf(2.f * (-x * kLn2 - logf(g)), 0.f);  // 2 ln(G*/g)
-      const float A = r3.w * q.den;                              // d^T P d, d = (x_n, y_n, 1)
-      depth = dn * (sstar - sqrtf(L / A));
-    }
+    depth = crossing_depth(r3, q, p.Tk, dn, a.flags);
   }
   const int64_t hw = (int64_t)width * height;
   const int64_t pix = (int64_t)py * width + px;
@@ -127,6 +152,8 @@ __device__ inline void write_pixel(const RenderFwdArgs& a, const PixFwd& p, cons
     o[hw + pix] = kNdcFar * kNdcNear / (kNdcFar - kNdcNear) * p.E;
     o[2 * hw + pix] = p.mu;
     o[3 * hw + pix] = p.M;
+    o[4 * hw + pix] = p.Pt;
+    o[5 * hw + pix] = __int_as_float(p.k >= 0 ? p.kpos : -1);
   }
 }
 
@@ -167,8 +194,10 @@ __global__ __launch_bounds__(TS * TS, MODE != kFwdPlain ? 1 : (W <= 8 ? 7 : (W =
   const float near_plane = a.near_plane;
 
   PixFwd p;
-  p.T = 1.f; p.r = p.g = p.b = 0.f; p.nx = p.ny = p.nz = 0.f; p.Tk = 0.f; p.n_emit = 0; p.k = -1;
+  p.T = 1.f; p.r = p.g = p.b = 0.f; p.nx = p.ny = p.nz = 0.f; p.Tk = 0.f; p.n_emit = 0; p.k = -1; p.kpos = -1;
   p.A = p.mu = p.M = p.E = 0.f;
+  p.sr = 0.f;
+  p.Pt = 1.f;
   float dn = 1.f;
   if constexpr (LOSS) {
     const float rx = (px + 0.5f - cam.cx) / cam.fx, ry = (py + 0.5f - cam.cy) / cam.fy;
@@ -234,9 +263,10 @@ __global__ __launch_bounds__(TS * TS, MODE != kFwdPlain ? 1 : (W <= 8 ? 7 : (W =
         record_fed(__float_as_uint(e.tag), key);
         if (win.push(key, al, __float_as_uint(e.tag), ea, et, ek)) {
           record_out(et);
+          const int k_before = p.k;
           const float w = blend(p, ea, et, a.app, cam_base);
           if constexpr (LOSS) {
-            if (w > 0.f) loss_terms(p, w, ek, et, a.geom, cam_base, px, py, dn);
+            if (w > 0.f) loss_terms(p, w, ek, et, a.geom, cam_base, px, py, dn, k_before < 0 && p.k >= 0, a.flags, near_plane);
           }
         }
       }
@@ -248,9 +278,10 @@ __global__ __launch_bounds__(TS * TS, MODE != kFwdPlain ? 1 : (W <= 8 ? 7 : (W =
       uint32_t et;
       win.pop_front(ea, et, ek);
       record_out(et);
+      const int k_before = p.k;
       const float w = blend(p, ea, et, a.app, cam_base);
       if constexpr (LOSS) {
-        if (w > 0.f) loss_terms(p, w, ek, et, a.geom, cam_base, px, py, dn);
+        if (w > 0.f) loss_terms(p, w, ek, et, a.geom, cam_base, px, py, dn, k_before < 0 && p.k >= 0, a.flags, near_plane);
       }
     }
   }

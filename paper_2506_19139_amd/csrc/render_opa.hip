@@ -1,10 +1,13 @@
 // Opacity field at the rendered depth (Sec. 3.3, direct opacity-field supervision): for each
 // pixel with a 0.5 crossing, O_N(x) at x = o + t_r d, t_r the depth the forward wrote, over
 // the Gaussians that pixel blends, each evaluated at min(t*, t_r) as in Eq. (12).  Whether a
-// Gaussian peaks in front of x is only known once t_r is, so this is a second pass: it
-// replays the forward's per-pixel order (same tile lists, candidate test and window) and
-// stops after the forward's blend count.  Only products are accumulated (O_N does not
-// depend on the order, App. A.2).
+// Gaussian peaks in front of x is only known once t_r is, so this is a second pass that
+// replays the forward's per-pixel order (same tile lists, candidate test and window).  As in
+// the paper, O_N = O_k + T_k sum_{i >= k} alpha_i prod_{k <= j < i} (1 - alpha_j): when the
+// forward ran with the loss outputs it already accumulated the factor from the crossing
+// Gaussian k on (1 - that sum = prod_{i >= k} (1 - alpha_i(x))), and this pass visits only
+// the Gaussians in front of k; without them it replays the whole blended sequence.  Only
+// products are accumulated (O_N does not depend on the order, App. A.2).
 #include "launch.h"
 #include "render_common.h"
 
@@ -40,18 +43,23 @@ __global__ __launch_bounds__(TS * TS, W <= 8 ? 8 : 1) void k_render_opa(RenderOp
   const int64_t hw = (int64_t)width * height;
   const int64_t pix = (int64_t)py * width + px;
   int n_emit = 0, kgid = -1;
-  float s_r = 0.f;
+  float s_r = 0.f, tail = 1.f;
   if (inside) {
     const float* aux = a.aux + kAuxChannels * ci.pix_off;
     n_emit = __float_as_int(aux[hw + pix]);
     kgid = __float_as_int(aux[2 * hw + pix]);
+    if (A.tail) {                                        // stop in front of k; the rest is known
+      const float* L = A.tail + kLossChannels * ci.pix_off;
+      tail = L[4 * hw + pix];
+      n_emit = __float_as_int(L[5 * hw + pix]);
+    }
     const float rx = (px + 0.5f - cam.cx) / cam.fx, ry = (py + 0.5f - cam.cy) / cam.fy;
     const float dn = sqrtf(fmaf(rx, rx, fmaf(ry, ry, 1.f)));
     s_r = a.depth[ci.pix_off + pix] / dn;
   }
   float P = 1.f;                       // prod (1 - alpha_j(x)) over the counted Gaussians
   int emitted = 0;
-  bool done = !inside || kgid < 0 || n_emit <= 0;
+  bool done = !inside || kgid < 0 || n_emit <= 0;     // (k first in the order: nothing in front)
   Window<W> win;
   win.init();
 
@@ -106,7 +114,7 @@ __global__ __launch_bounds__(TS * TS, W <= 8 ? 8 : 1) void k_render_opa(RenderOp
     }
   }
   if (!inside) return;
-  A.opa[ci.pix_off + pix] = kgid >= 0 ? 1.f - P : 0.f;
+  A.opa[ci.pix_off + pix] = kgid >= 0 ? 1.f - P * tail : 0.f;
 }
 
 template <int TS>

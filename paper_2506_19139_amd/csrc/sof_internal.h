@@ -140,7 +140,7 @@ inline __host__ __device__ uint32_t float_order_bits(float f) {
 
 // NDC mapping of the distortion and extent losses (near 0.2, far 100 on the ray distance)
 constexpr float kNdcNear = 0.2f, kNdcFar = 100.f;
-constexpr int kLossChannels = 4;
+constexpr int kLossChannels = 6;   // distortion, extent, mean, moment, opacity tail, position of k
 
 // Depth key of the query's tile lists.  shift < 0: the exact order of the float.  Otherwise
 // a monotone integer quantisation of it: offset of the float's order bits above those of

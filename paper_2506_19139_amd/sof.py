@@ -28,7 +28,7 @@ SOF_QUERY_REUSE = 1 << 4
 
 WINDOWS = (0, 1, 2, 4, 8, 16, 32)
 AUX_CHANNELS = 6      # T_end, n_emitted, k, T_k, entries tested, candidates
-LOSS_CHANNELS = 4     # distortion, extent, sum w d, sum w d^2
+LOSS_CHANNELS = 6     # distortion, extent, mean and moment of d, opacity tail, position of k
 TILES = (8, 16, 32)
 
 
@@ -71,7 +71,7 @@ _SIGS = {
     "sof_render_order": (ctypes.c_int, [ctypes.c_int64, _P, _P, ctypes.c_int32, _P, _P, ctypes.c_size_t, _P,
                                         ctypes.c_size_t, _P, ctypes.c_int64, ctypes.c_int32, _P, _P, _P, _P, _P]),
     "sof_render_opacity": (ctypes.c_int, [ctypes.c_int64, _P, _P, ctypes.c_int32, _P, _P, ctypes.c_size_t, _P,
-                                          ctypes.c_size_t, _P, _P, _P, _P]),
+                                          ctypes.c_size_t, _P, _P, _P, _P, _P]),
     "sof_render_bwd": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, _P, _P, ctypes.c_size_t, _P, ctypes.c_size_t,
                                       _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P, _P,
                                       _P, _P, _P, _P]),
@@ -254,11 +254,11 @@ def render_order(n, cams: Cameras, opts: Options, proj, bins, slot, n_slots, max
     return stream_ids[:n_slots], stream_keys[:n_slots], emit_ids[:n_slots], counts[:n_slots]
 
 
-def render_opacity(n, cams: Cameras, opts: Options, proj, bins, depth, aux, opacity):
+def render_opacity(n, cams: Cameras, opts: Options, proj, bins, depth, aux, opacity, losses=None):
     o = opts.c_struct()
     _check(lib().sof_render_opacity(n, cams.hp(), cams.dp(), len(cams), ctypes.byref(o), _ptr(proj), proj.numel(),
-                                    _ptr(bins), bins.numel(), _ptr(depth), _ptr(aux), _ptr(opacity), _stream()),
-           "sof_render_opacity")
+                                    _ptr(bins), bins.numel(), _ptr(depth), _ptr(aux), _ptr(losses), _ptr(opacity),
+                                    _stream()), "sof_render_opacity")
 
 
 def render_bwd(g: Gaussians, cams: Cameras, opts: Options, proj, bins, rgb, normal, aux, d_rgb, d_acc, d_depth,
@@ -492,12 +492,16 @@ class Rasterizer:
             res.append(cam_res)
         return res
 
-    def opacity(self, g: Gaussians, out):
+    def opacity(self, g: Gaussians, out, split=True):
         """Opacity field at each pixel's rendered depth (second pass after forward); stored in
-        out["opa"] (0 where a pixel has no 0.5 crossing)."""
+        out["opa"] (0 where a pixel has no 0.5 crossing).  With split (and a forward run with
+        losses=True) the pass visits only the Gaussians in front of the crossing and takes the
+        rest from the forward; otherwise it replays every blended Gaussian."""
         if "opa" not in out:
             out["opa"] = torch.empty(self.cams.n_pixels, device=self.device)
-        render_opacity(g.n, self.cams, self.opts, self.proj, self.bins, out["depth"], out["aux"], out["opa"])
+        losses = out.get("losses") if split else None
+        render_opacity(g.n, self.cams, self.opts, self.proj, self.bins, out["depth"], out["aux"], out["opa"],
+                       losses=losses)
         return out["opa"]
 
     def backward(self, g: Gaussians, out, d_rgb=None, d_acc=None, d_depth=None, d_normal=None, grads_out=None,

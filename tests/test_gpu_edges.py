@@ -19,7 +19,7 @@ def test_empty_scene_gives_zero_losses_and_opacity():
     d = torch.ones(2 * 32 * 32, device="cuda")
     gr = r.backward(g, out, d_rgb=torch.ones_like(out["rgb"]), d_opa=torch.ones_like(opa), d_losses=d)
     torch.cuda.synchronize()
-    assert torch.count_nonzero(out["losses"].view(4, -1)[:2]).item() == 0
+    assert torch.count_nonzero(out["losses"].view(sof.LOSS_CHANNELS, -1)[:2]).item() == 0
     assert torch.count_nonzero(opa).item() == 0
     assert all(v.numel() == 0 for v in gr.values())
 

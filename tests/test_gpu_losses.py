@@ -25,7 +25,7 @@ def test_losses_full_frame(tile, window):
     host = {k: v.cpu().numpy() for k, v in out.items()}
     gpu = unpack(host, [cam])
     W, H = cam["width"], cam["height"]
-    L = host["losses"].reshape(4, H * W)
+    L = host["losses"].reshape(sof.LOSS_CHANNELS, H * W)
     sc, oc = oracle_scene_cam(scene, cam)
     v = O.view(sc, oc)
     worst = [0.0, 0.0]

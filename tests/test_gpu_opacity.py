@@ -20,10 +20,20 @@ NAMES = ("means", "scales", "quats", "opac", "sh")
 
 @pytest.mark.parametrize("tile,window", [(16, 8), (8, 4), (16, 0)])
 def test_opacity_at_depth_full_frame(tile, window):
+    """Both ways of computing it: the paper's split (the forward accumulates the part from the
+    crossing Gaussian k on, the second pass visits only the Gaussians in front of k) and the
+    full replay of the blended sequence; they agree to float rounding."""
     scene, cam = scenes.small_scene(), scenes.small_camera()
     print(f"[case] opacity pass, small scene 64x64 tile {tile} window {window}", flush=True)
-    r, g, C, opts, out, host = gpu_render(scene, [cam], tile=tile, window=window)
-    opa = r.opacity(g, out).cpu().numpy()
+    g = sof.Gaussians.from_numpy(scene)
+    r = sof.Rasterizer(sof.Cameras([cam]), sof.Options(tile=tile, window=window))
+    out = r.forward(g, losses=True)
+    opa = r.opacity(g, out, split=True).clone().cpu().numpy()
+    full = r.opacity(g, out, split=False).cpu().numpy()
+    print(f"  split vs full replay: max difference {np.abs(opa - full).max():.2e}")
+    assert np.abs(opa - full).max() <= 2e-6
+    torch.cuda.synchronize()
+    host = {k: v.cpu().numpy() for k, v in out.items()}
     gpu = unpack(host, [cam])
     sc, oc = oracle_scene_cam(scene, cam)
     v = O.view(sc, oc)
@@ -67,7 +77,7 @@ def test_opacity_gradient_matches_finite_differences(seed, window):
     w_opa = rng.normal(0, 1, P)
     g = sof.Gaussians.from_numpy(scene)
     rast = sof.Rasterizer(sof.Cameras([cam]), sof.Options(tile=8, window=window))
-    out = rast.forward(g)
+    out = rast.forward(g, losses=seed % 2 == 0)        # even seeds: the split opacity pass
     rast.opacity(g, out)
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda()
     gr = rast.backward(g, out, dev(up[:, 0:3].T.reshape(-1)), dev(up[:, 3]), dev(up[:, 4]), dev(up[:, 5:8].T.reshape(-1)),
