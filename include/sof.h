@@ -133,7 +133,9 @@ size_t sof_read_status_offset(void);
 /*
  * sof_project -- Sec. 3.1 (Eq. (3), (7)-(10)), App. A.1.
  * For every camera c and Gaussian i writes into `proj` the record the rasteriser needs:
- * liveness (o >= 1/255 and view z of the mean > near_plane), the quadric constants of the
+ * liveness (o >= 1/255 and view z of the mean > near_plane; a Gaussian with a non-finite
+ * mean, scale, quaternion, opacity or colour, a scale <= 0 or a zero quaternion is culled
+ * as well, so it touches no tile and contributes nothing), the quadric constants of the
  * pixel-ray evaluation (computed in float64, stored in float32 in a cancellation-free form
  * relative to the projected centre), opacity, colour max(0, SH(dir) + 1/2) with dir from
  * the camera centre to the mean, the normal (shortest axis, facing the camera), the

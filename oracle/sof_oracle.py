@@ -242,9 +242,13 @@ class CameraView:
     normal: np.ndarray     # [N,3]
 
 
-def view(scene: Scene, cam: Camera) -> CameraView:
+def view(scene: Scene, cam: Camera, appearance=True) -> CameraView:
+    """Per-camera liveness, precisions and level-0 keys; appearance=False skips the colours and
+    normals (the opacity field of Eq. (12) never reads them)."""
     mu_c = scene.means @ cam.R.T + cam.t[None, :]
     live = (scene.opac >= ALPHA_MIN) & (mu_c[:, 2] > NEAR)
+    if not appearance:
+        return CameraView(cam, live, scene.precisions(), mu_c[:, 2].astype(np.float32), None, None)
     return CameraView(cam, live, scene.precisions(), mu_c[:, 2].astype(np.float32),
                       gaussian_colors(scene, cam.center), gaussian_normals(scene, cam.center))
 

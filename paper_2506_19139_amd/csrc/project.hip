@@ -53,7 +53,14 @@ __global__ __launch_bounds__(256) void k_project(ProjectArgs a) {
   const double mcy = Rc[3] * mx + Rc[4] * my + Rc[5] * mz_w + cam.t[1];
   const double mcz = Rc[6] * mx + Rc[7] * my + Rc[8] * mz_w + cam.t[2];
 
-  const bool live = (o >= kAlphaMin) && (mcz > (double)a.near_plane);
+  // a Gaussian with a non-finite or degenerate parameter (scale <= 0, zero quaternion) is
+  // culled like a dead one, so that it can neither poison a pixel nor waste tile instances
+  double qw = a.quats[4 * i], qx = a.quats[4 * i + 1], qy = a.quats[4 * i + 2], qz = a.quats[4 * i + 3];
+  const double s0 = a.scales[3 * i], s1 = a.scales[3 * i + 1], s2 = a.scales[3 * i + 2];
+  const double qq = qw * qw + qx * qx + qy * qy + qz * qz;
+  const bool sane = isfinite(mcx) && isfinite(mcy) && isfinite(mcz) && isfinite(o) && s0 > 0.0 && s1 > 0.0 && s2 > 0.0 &&
+                    isfinite(s0 * s1 * s2) && qq > 0.0 && isfinite(qq);
+  const bool live = sane && (o >= kAlphaMin) && (mcz > (double)a.near_plane);
   if (!live) {
     a.rect[idx] = make_short4(0, 0, -1, -1);
     a.zmin[idx] = 0.f;
@@ -61,8 +68,7 @@ __global__ __launch_bounds__(256) void k_project(ProjectArgs a) {
   }
 
   // rotation of the Gaussian and its camera-space frame T = Rc Rg
-  double qw = a.quats[4 * i], qx = a.quats[4 * i + 1], qy = a.quats[4 * i + 2], qz = a.quats[4 * i + 3];
-  const double qn = rsqrt(qw * qw + qx * qx + qy * qy + qz * qz);
+  const double qn = rsqrt(qq);
   qw *= qn; qx *= qn; qy *= qn; qz *= qn;
   double Rg[9];
   quat_rot<double>(qw, qx, qy, qz, Rg);
@@ -71,7 +77,6 @@ __global__ __launch_bounds__(256) void k_project(ProjectArgs a) {
   for (int r = 0; r < 3; ++r)
 #pragma unroll
     for (int k = 0; k < 3; ++k) T[3 * r + k] = Rc[3 * r] * Rg[k] + Rc[3 * r + 1] * Rg[3 + k] + Rc[3 * r + 2] * Rg[6 + k];
-  const double s0 = a.scales[3 * i], s1 = a.scales[3 * i + 1], s2 = a.scales[3 * i + 2];
   const double v0 = s0 * s0, v1 = s1 * s1, v2 = s2 * s2;
   const double w0 = 1.0 / v0, w1 = 1.0 / v1, w2 = 1.0 / v2;
   // Sigma_c = T diag(v) T^T, P = T diag(1/v) T^T (symmetric; index pairs 00 01 02 11 12 22)
@@ -185,6 +190,7 @@ __global__ __launch_bounds__(256) void k_project(ProjectArgs a) {
   if (nx * (ccx - mx) + ny * (ccy - my) + nz * (ccz - mz_w) < 0.0) { nx = -nx; ny = -ny; nz = -nz; }
   a.app[2 * idx + 0] = make_float4(fmaxf(cr, 0.f), fmaxf(cg, 0.f), fmaxf(cb, 0.f), o);
   a.app[2 * idx + 1] = make_float4((float)nx, (float)ny, (float)nz, 0.f);
+  if (!isfinite(cr + cg + cb)) a.rect[idx] = make_short4(0, 0, -1, -1);   // non-finite SH: culled too
 }
 
 // World record for point queries: row k of S^-1 R^T is (column k of R) / s_k.

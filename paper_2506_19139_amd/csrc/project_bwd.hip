@@ -50,10 +50,12 @@ __global__ __launch_bounds__(kPbThreads) void k_project_bwd(ProjectBwdArgs a) {
 #pragma unroll
   for (int k = 0; k < K3; ++k) dsh[k] = 0.f;
 
+  bool touched = false;                     // some camera has an instance of this Gaussian
   for (int c = 0; c < a.n_cams; ++c) {
     const int64_t vg = (int64_t)c * a.n + i;
     const int cnt = a.counts[vg];
     if (cnt == 0) continue;
+    touched = true;
     const int64_t e0 = a.offsets[vg];
     const int64_t e1 = (e0 + cnt < kinst) ? e0 + cnt : kinst;
     float gsum[kGradFields];
@@ -146,14 +148,16 @@ __global__ __launch_bounds__(kPbThreads) void k_project_bwd(ProjectBwdArgs a) {
   const double qd = w * dq[0] + x * dq[1] + y * dq[2] + z * dq[3];
   const double qv[4] = {w, x, y, z};
   float* sm = s_small + threadIdx.x * 11;
+  // an untouched Gaussian (culled everywhere, possibly for non-finite parameters) gets exact
+  // zeros rather than 0 times its own non-finite chain-rule factors
   for (int k = 0; k < 3; ++k) {
-    sm[k] = (float)dmu[k];
-    sm[3 + k] = (float)ds[k];
+    sm[k] = touched ? (float)dmu[k] : 0.f;
+    sm[3 + k] = touched ? (float)ds[k] : 0.f;
   }
-  for (int k = 0; k < 4; ++k) sm[6 + k] = (float)((dq[k] - qv[k] * qd) / qnorm);
-  sm[10] = (float)dop;
+  for (int k = 0; k < 4; ++k) sm[6 + k] = touched ? (float)((dq[k] - qv[k] * qd) / qnorm) : 0.f;
+  sm[10] = touched ? (float)dop : 0.f;
 #pragma unroll
-  for (int k = 0; k < K3; ++k) s_sh[threadIdx.x * K3 + k] = dsh[k];
+  for (int k = 0; k < K3; ++k) s_sh[threadIdx.x * K3 + k] = touched ? dsh[k] : 0.f;
   }
   __syncthreads();
   if (rows <= 0) return;

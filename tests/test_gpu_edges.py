@@ -53,3 +53,99 @@ def test_bisection_with_no_edges():
     g = sof.Gaussians.from_numpy(scenes.small_scene(50, seed=5))
     out = search(g, a.clone(), a.clone(), steps=8)
     assert out.shape == (0, 3)
+
+
+def _poison(scene, rng):
+    """Copy of a scene with non-finite or degenerate parameters planted in some Gaussians;
+    returns it and the indices of the poisoned ones."""
+    s = {k: (v.copy() if k != "sh_degree" else v) for k, v in scene.items()}
+    n = len(s["opac"])
+    bad = rng.choice(n, 36, replace=False)
+    kinds = np.arange(len(bad)) % 9
+    for i, kind in zip(bad, kinds):
+        if kind == 0: s["means"][i, 0] = np.nan
+        elif kind == 1: s["means"][i, 2] = np.inf
+        elif kind == 2: s["means"][i, 1] = -np.inf
+        elif kind == 3: s["scales"][i, 1] = np.nan
+        elif kind == 4: s["scales"][i, 2] = 0.0
+        elif kind == 5: s["quats"][i] = 0.0
+        elif kind == 6: s["quats"][i, 3] = np.inf
+        elif kind == 7: s["opac"][i] = np.nan
+        else: s["sh"][i, 0, 1] = np.nan
+    return s, np.sort(bad)
+
+
+def test_non_finite_gaussians_are_culled():
+    """Gaussians with a NaN / Inf mean, scale, quaternion, opacity or SH coefficient, a zero
+    scale or a zero quaternion touch no tile: the image equals the render of the scene without
+    them bit for bit, and the backward gives them zero gradients and the rest those of the
+    clean scene."""
+    rng = np.random.default_rng(11)
+    scene, cam = scenes.small_scene(1000, seed=0), scenes.small_camera()
+    dirty, bad = _poison(scene, rng)
+    keep = np.setdiff1d(np.arange(1000), bad)
+    clean = scenes.subset_scene(scene, keep)
+    print(f"[case] {len(bad)} poisoned Gaussians in the small scene", flush=True)
+    res = []
+    for s in (dirty, clean):
+        g = sof.Gaussians.from_numpy(s)
+        r = sof.Rasterizer(sof.Cameras([cam]), sof.Options(tile=16, window=8))
+        out = r.forward(g)
+        P = 64 * 64
+        gr = r.backward(g, out, d_rgb=torch.ones_like(out["rgb"]) / P, d_acc=torch.ones_like(out["acc"]) / P,
+                        d_depth=torch.ones_like(out["depth"]) / P, d_normal=torch.ones_like(out["normal"]) / P)
+        torch.cuda.synchronize()
+        res.append(({k: v.cpu().numpy() for k, v in out.items()}, {k: v.cpu().numpy() for k, v in gr.items()},
+                    sof.read_status(r.bins)[0]))
+    (od, gd, kd), (oc, gc, kc) = res
+    assert kd == kc                                   # no instance for a poisoned Gaussian
+    for k in ("rgb", "acc", "depth", "normal"):
+        assert np.array_equal(od[k].view(np.uint32), oc[k].view(np.uint32)), k
+    kk = od["aux"].reshape(sof.AUX_CHANNELS, -1)[2].view(np.int32)
+    kc_ = oc["aux"].reshape(sof.AUX_CHANNELS, -1)[2].view(np.int32)
+    assert np.array_equal(kk, np.where(kc_ >= 0, keep[np.maximum(kc_, 0)], -1))
+    for k in gd:
+        assert np.all(np.isfinite(gd[k])), k
+        assert np.all(gd[k][bad] == 0), k
+        ref = gc[k]
+        err = np.abs(gd[k][keep] - ref).max() / max(np.abs(ref).max(), 1e-30)
+        assert err <= 1e-5, (k, err)
+
+
+def test_capacity_overflow_writes_nothing_out_of_bounds():
+    """With the instance capacity far below the need, every buffer the library writes is
+    followed by a guard region that must stay as it was; the status word reports the
+    overflow and the outputs stay finite."""
+    scene, cam = scenes.small_scene(1000, seed=0), scenes.small_camera()
+    g = sof.Gaussians.from_numpy(scene)
+    C = sof.Cameras([cam])
+    opts = sof.Options(tile=16, window=8, capacity=100)
+    pb, bb, gb = sof.workspace_size(g.n, C, opts)
+    GUARD = 1 << 16
+
+    def guarded(nbytes):
+        t = torch.full((nbytes + GUARD,), 0xA5, dtype=torch.uint8, device="cuda")
+        return t, t[:nbytes]
+    proj_all, proj = guarded(pb)
+    bins_all, bins = guarded(bb)
+    grads_all, grads = guarded(gb)
+    P = C.n_pixels
+    outs = {k: guarded(4 * c * P) for k, c in (("rgb", 3), ("acc", 1), ("depth", 1), ("normal", 3),
+                                                ("aux", sof.AUX_CHANNELS))}
+    view = {k: v[1].view(torch.float32) for k, v in outs.items()}
+    print("[case] capacity 100 with guard regions", flush=True)
+    sof.project(g, C, opts, proj)
+    sof.bin_sort(g.n, C, opts, proj, bins)
+    sof.render_fwd(g.n, C, opts, proj, bins, view["rgb"], view["acc"], view["depth"], view["normal"], view["aux"])
+    d = [torch.empty_like(t) for t in (g.means, g.scales, g.quats, g.opac, g.sh)]
+    sof.render_bwd(g, C, opts, proj, bins, view["rgb"], view["normal"], view["aux"], torch.ones_like(view["rgb"]),
+                   None, None, None, grads, *d)
+    torch.cuda.synchronize()
+    k, flags = sof.read_status(bins)
+    assert k > 100 and (flags & 1) == 1
+    for name, (full, used) in [("proj", (proj_all, proj)), ("bins", (bins_all, bins)), ("grads", (grads_all, grads))] + \
+            [(k_, v) for k_, v in outs.items()]:
+        tail = full[used.numel():].cpu().numpy()
+        assert np.all(tail == 0xA5), name
+    assert all(np.all(np.isfinite(v.cpu().numpy())) for v in (view["rgb"], view["acc"], view["depth"]))
+    assert all(np.all(np.isfinite(t.cpu().numpy())) for t in d)
