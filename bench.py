@@ -37,49 +37,70 @@ FLOP_BLEND = 15     # one blended Gaussian: transmittance, weight, colour and no
 FLOP_ADJ = 110      # one replayed Gaussian in the backward: dalpha, chain to (mu_c, P_c), partials
 
 
-# HBM traffic of the rasteriser kernels, from two rocprofv3 --pmc passes (FETCH_SIZE, then
-# WRITE_SIZE) over this benchmark with its default arguments, in KiB per dispatch, each scaled by
-# what the same counter reads for a 1 GiB device copy (--calib-copy-mib 1024).  A figure is
-# reported only while the kernel's sources hash to the value the counters were taken with.
-KERNEL_SOURCES = {
-    "k_render_fwd": ("render_fwd.hip", "render_common.h", "sof_internal.h", "launch.h"),
-    "k_render_bwd": ("render_bwd.hip", "render_common.h", "sof_internal.h", "launch.h"),
-}
-COUNTERS = {                        # kernel -> sources hash, counter KiB per dispatch, SQ_INSTS_VALU
-    "k_render_bwd": {"src": "e43c02028bc3aae5", "fetch_kib": 686727.8, "write_kib": 211851.3, "valu": 2.0436e9},
-    "k_render_fwd": {"src": "c50ee27622f6d01e", "fetch_kib": 353514.4, "write_kib": 148958.0, "valu": 7.409e8},
-}
+# Counter figures (HBM bytes, vector and LDS instructions) are taken with rocprofv3 over this
+# benchmark and written by `bench.py --summarize` into the profile summary below, one line per
+# kernel with the hash of the sources the kernel is built from.  The bench line reports a
+# kernel's counter figures only while its sources still hash to that value and the workload is
+# the default one; a changed source needs a new measurement.
+PROFILE = os.path.join(ROOT, "profiles", "step_1M_1080p_and_query_3M_27M_counters.txt")
+CSRC = os.path.join(ROOT, "paper_2506_19139_amd", "csrc")
 VALU_CYCLES = 4                     # a wave64 vector instruction holds a 16-lane SIMD for 4 cycles
 N_SIMDS, CLOCK_GHZ = 1024, 2.4      # 256 CUs x 4 SIMDs
-COUNTER_SCALE = {"fetch": 0.50002, "write": 1.0}    # counter KiB per KiB moved by the 1 GiB copy
 
 
-def kernel_source_hash(kernel):
+def kernel_short_name(full):
+    """`void sof::k_render_bwd<16, 8, false>(sof::RenderBwdArgs)` -> `k_render_bwd<16, 8, false>`."""
+    n = full.split("(")[0]
+    n = n.split("sof::")[-1] if "sof::" in n else n.split()[-1]
+    return n.strip()
+
+
+def kernel_source_file(short):
+    """The .hip file of csrc that defines the kernel (None for kernels from other libraries)."""
+    import re
+    base = short.split("<")[0]
+    for f in sorted(os.listdir(CSRC)):
+        if f.endswith(".hip") and re.search(r"void\s+" + re.escape(base) + r"\s*\(", open(os.path.join(CSRC, f)).read()):
+            return f
+    return None
+
+
+def kernel_source_hash(short):
+    """Hash of the kernel's .hip file, every header of csrc and the public header."""
     import hashlib
+    f = kernel_source_file(short)
+    if f is None:
+        return None
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES[kernel]:
-        with open(os.path.join(ROOT, "paper_2506_19139_amd", "csrc", f), "rb") as fh:
+    for name in [f] + sorted(x for x in os.listdir(CSRC) if x.endswith(".h")):
+        with open(os.path.join(CSRC, name), "rb") as fh:
             h.update(fh.read())
+    with open(os.path.join(ROOT, "include", "sof.h"), "rb") as fh:
+        h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel, args):
-    c = COUNTERS.get(kernel)
-    default = (args.n, args.tile, args.window) == (1_000_000, 16, 8)
-    if not c or not default or None in COUNTER_SCALE.values() or c["src"] != kernel_source_hash(kernel):
-        return None
-    return round((c["fetch_kib"] / COUNTER_SCALE["fetch"] + c["write_kib"] / COUNTER_SCALE["write"]) * 1024)
+def read_profile(path=PROFILE):
+    """Per-kernel records of a profile summary (lines `kernel=... src=... key=value ...`)."""
+    rec = {}
+    if not os.path.exists(path):
+        return rec
+    for line in open(path):
+        if not line.startswith("kernel="):
+            continue
+        fields = dict(tok.split("=", 1) for tok in line.strip().split("\t"))
+        rec[fields["kernel"]] = fields
+    return rec
 
 
-def measured_issue(kernel, args, kernel_ms):
-    """Vector-issue time of the kernel's VALU wave instructions (SQ_INSTS_VALU, same counter
-    pass rules as the traffic) on every SIMD of the chip, and its share of the measured time."""
-    c = COUNTERS.get(kernel)
+def counter_figures(short, args, profile=None):
+    """Counter figures of one kernel from the profile, or None when they do not apply (another
+    workload, or sources changed since they were taken)."""
     default = (args.n, args.tile, args.window) == (1_000_000, 16, 8)
-    if not c or not default or c["src"] != kernel_source_hash(kernel):
+    rec = (profile if profile is not None else read_profile()).get(short)
+    if not default or not rec or rec.get("src") != kernel_source_hash(short):
         return None
-    issue_ms = c["valu"] * VALU_CYCLES / (N_SIMDS * CLOCK_GHZ * 1e9) * 1e3
-    return {"valu_wave_insts": c["valu"], "issue_ms": round(issue_ms, 4), "frac": round(issue_ms / kernel_ms, 3)}
+    return rec
 
 
 def parse():
@@ -107,9 +128,18 @@ def parse():
                     help="skip the level-set query and the binary search")
     ap.add_argument("--no-multiview", action="store_true",
                     help="skip the 8-camera graph-captured training step")
-    ap.add_argument("--cpu-pixels", type=int, default=160)
+    ap.add_argument("--cpu-pixels", type=int, default=512)
+    ap.add_argument("--cpu-query-points", type=int, default=4)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one device copy of this many MiB first (scale reference for HBM byte counters)")
+    ap.add_argument("--no-peaks", action="store_true", help="skip the measured copy and FMA peaks")
+    ap.add_argument("--summarize", default=None,
+                    help="write a profile summary to this file from --trace-db/--read-db/--write-db/--sq-db and exit")
+    ap.add_argument("--trace-db")
+    ap.add_argument("--read-db")
+    ap.add_argument("--write-db")
+    ap.add_argument("--sq-db")
+    ap.add_argument("--header", default="", help="text put at the top of the summary (\\n for new lines)")
     return ap.parse_args()
 
 
@@ -117,56 +147,185 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+# --------------------------------------------------------------------------- profile summary
+
+READ_COUNTERS = ("TCC_EA0_RDREQ", "TCC_EA0_RDREQ_32B", "TCC_EA0_RDREQ_64B", "TCC_EA0_RDREQ_128B")
+WRITE_COUNTERS = ("TCC_EA0_WRREQ", "TCC_EA0_WRREQ_64B")
+SQ_COUNTERS = ("SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS", "SQ_LDS_BANK_CONFLICT",
+               "SQ_INSTS_VMEM", "SQ_BUSY_CYCLES", "SQ_WAIT_INST_LDS")
+
+
+def _db_trace(db):
+    import sqlite3
+    import collections
+    cur = sqlite3.connect(db).cursor()
+    out = collections.defaultdict(list)
+    for name, t0, t1 in cur.execute("select name, start, end from kernels"):
+        out[kernel_short_name(name)].append((t1 - t0) / 1e3)
+    return out
+
+
+def _db_counters(db):
+    import sqlite3
+    import collections
+    cur = sqlite3.connect(db).cursor()
+    out = collections.defaultdict(lambda: collections.defaultdict(list))
+    for name, counter, value in cur.execute("select kernel_name, counter_name, value from counters_collection"):
+        out[kernel_short_name(name)][counter].append(float(value))
+    return out
+
+
+def summarize(args):
+    """Write the profile summary from the rocprofv3 databases of this benchmark: one kernel trace
+    and three counter passes (read requests by size, write requests by size, SQ instruction
+    counts).  HBM bytes are counted from request sizes (32 x 32B + 64 x 64B + 128 x 128B reads,
+    32 / 64 B writes) and checked against a streaming copy of known size run in the same passes."""
+    trace = _db_trace(args.trace_db)
+    rd, wr, sq = _db_counters(args.read_db), _db_counters(args.write_db), _db_counters(args.sq_db)
+    avg = lambda v: sum(v) / len(v) if v else 0.0
+
+    def read_bytes(c):
+        return (32 * avg(c.get("TCC_EA0_RDREQ_32B", [])) + 64 * avg(c.get("TCC_EA0_RDREQ_64B", []))
+                + 128 * avg(c.get("TCC_EA0_RDREQ_128B", [])))
+
+    def write_bytes(c):
+        n, n64 = avg(c.get("TCC_EA0_WRREQ", [])), avg(c.get("TCC_EA0_WRREQ_64B", []))
+        return 64 * n64 + 32 * (n - n64)
+    copy_bytes = args.calib_copy_mib * (1 << 20)
+    cal_r = read_bytes(rd["k_peak_copy"]) / copy_bytes if "k_peak_copy" in rd else None
+    cal_w = write_bytes(wr["k_peak_copy"]) / copy_bytes if "k_peak_copy" in wr else None
+    lines = []
+    for k in sorted(trace, key=lambda k: -sum(trace[k])):
+        src = kernel_source_hash(k)
+        if src is None or k.startswith("k_peak"):
+            continue
+        t = avg(trace[k])
+        rb, wb = read_bytes(rd.get(k, {})), write_bytes(wr.get(k, {}))
+        c = sq.get(k, {})
+        valu = avg(c.get("SQ_INSTS_VALU", []))
+        issue_us = valu * VALU_CYCLES / (N_SIMDS * CLOCK_GHZ * 1e9) * 1e6
+        f = {"kernel": k, "src": src, "calls": len(trace[k]), "avg_us": f"{t:.2f}", "read_bytes": f"{rb:.0f}",
+             "write_bytes": f"{wb:.0f}", "GBps": f"{(rb + wb) / (t * 1e-6) / 1e9:.1f}",
+             "hbm_frac": f"{(rb + wb) / (t * 1e-6) / (HBM_PEAK_GBS * 1e9):.4f}",
+             "valu": f"{valu:.4g}", "salu": f"{avg(c.get('SQ_INSTS_SALU', [])):.4g}",
+             "lds": f"{avg(c.get('SQ_INSTS_LDS', [])):.4g}",
+             "lds_bank_conflict": f"{avg(c.get('SQ_LDS_BANK_CONFLICT', [])):.4g}",
+             "valu_issue_us": f"{issue_us:.2f}", "issue_frac": f"{issue_us / t:.3f}"}
+        lines.append("\t".join(f"{a}={b}" for a, b in f.items()))
+    with open(args.summarize, "w") as fh:
+        fh.write(args.header.replace("\\n", "\n") + "\n" if args.header else "")
+        fh.write(f"calibration: streaming copy of {copy_bytes} bytes read as {cal_r:.4f} x its size (reads) and "
+                 f"{cal_w:.4f} x (writes) by the request-size counts; bytes below are the counts, unscaled\n"
+                 if cal_r is not None and cal_w is not None else "calibration: no copy in the counter passes\n")
+        fh.write("fields: avg_us = kernel-trace average duration; read/write_bytes per dispatch from TCC_EA0 "
+                 "request counts by size; GBps and hbm_frac (of 8 TB/s) over avg_us; valu/salu/lds = SQ_INSTS_* "
+                 "wave instructions per dispatch; lds_bank_conflict = SQ_LDS_BANK_CONFLICT cycles; valu_issue_us "
+                 "= valu x 4 cycles / (1024 SIMDs x 2.4 GHz) and issue_frac its share of avg_us; src = hash of the "
+                 "kernel's sources (bench.py kernel_source_hash)\n")
+        for l in lines:
+            fh.write(l + "\n")
+    print(f"wrote {args.summarize}: {len(lines)} kernels", file=sys.stderr)
+
+
 # --------------------------------------------------------------------------- CPU oracle
 
 _CPU = {}
 
 
+def _oracle_view_chunk(ids):
+    """Camera view of a chunk of the scene's Gaussians (colours, normals, precisions)."""
+    from oracle import sof_oracle as O
+    from paper_2506_19139_amd import scenes
+    sc = O.Scene.from_arrays(**scenes.subset_scene(_CPU["scene"], ids))
+    v = O.view(sc, _CPU["ocam"])
+    return v.live, v.prec, v.zkey32, v.color, v.normal
+
+
 def _oracle_pixel(px_py):
     from oracle import sof_oracle as O
-    sc, v, window = _CPU["sc"], _CPU["v"], _CPU["window"]
-    r = O.render_pixel(sc, v, px_py[0], px_py[1], window)
+    r = O.render_pixel(_CPU["sc"], _CPU["v"], px_py[0], px_py[1], _CPU["window"])
     return r.acc
 
 
-def cpu_baseline(scene, cam, window, n_pixels, stride=10):
-    """The oracle as it stands, on the host cores, on a bounded sample of the workload:
-    every `stride`-th Gaussian and `n_pixels` random pixels.  The oracle's cost is linear in
-    the number of Gaussians (per-frame setup and per-pixel brute force) and in the number of
-    pixels, so the sample rate is scaled by `stride` and extrapolated to the full frame."""
-    import multiprocessing as mp
+def _oracle_query_chunk(ids):
+    """prod (1 - alpha_i(x)) over a chunk of the Gaussians for every (sampled point, view), and
+    whether the view sees the point: the opacity field factorises over Gaussians (App. A.2)."""
     from oracle import sof_oracle as O
     from paper_2506_19139_amd import scenes
+    sc = O.Scene.from_arrays(**scenes.subset_scene(_CPU["qscene"], ids))
+    views = O.views_geometry(sc, _CPU["qcams"])
+    pts = _CPU["qpts"]
+    prod = np.ones((len(pts), len(views)))
+    for i, x in enumerate(pts):
+        for j, v in enumerate(views):
+            _, alpha = O.view_alphas(sc, v, x)
+            prod[i, j] = float(np.prod(1.0 - alpha))
+    return prod
+
+
+def cpu_baseline(scene, cam, window, n_pixels, qscene=None, qcams=None, qpts=None, n_query_total=0):
+    """The oracle as it stands, on the host cores, on bounded samples of the two workloads.
+
+    Render: the camera view of all N Gaussians (computed in Gaussian chunks, one per process),
+    then `n_pixels` random pixels of the frame by brute force over all N, one per process;
+    extrapolated linearly to the full frame.  Query: the sampled points against all Gaussians
+    and all views, the product over Gaussians split into chunks (one per process) and combined,
+    then the minimum over the views that see each point; extrapolated to all points."""
+    import multiprocessing as mp
+    from oracle import sof_oracle as O
     cores = len(os.sched_getaffinity(0))
-    workers = max(1, min(cores, 16))
-    sub = scenes.subset_scene(scene, np.arange(0, scene["means"].shape[0], stride))
-    t0 = time.perf_counter()
-    sc = O.Scene.from_arrays(**sub)
+    workers = max(1, min(cores, 15))
+    ctx = mp.get_context("fork")
+    n = scene["means"].shape[0]
+    chunks = np.array_split(np.arange(n), workers)
     oc = O.Camera.from_arrays(**cam)
-    v = O.view(sc, oc)
+    _CPU.update(scene=scene, ocam=oc, window=window)
+    t0 = time.perf_counter()
+    with ctx.Pool(workers) as pool:
+        parts = pool.map(_oracle_view_chunk, chunks)
+    v = O.CameraView(oc, *(np.concatenate([p[k] for p in parts]) for k in range(5)))
     t_setup = time.perf_counter() - t0
+    log(f"cpu baseline: view of {n} Gaussians in {t_setup:.1f} s")
+    _CPU.update(sc=O.Scene.from_arrays(**scene), v=v)
     rng = np.random.default_rng(0)
     pix = [(int(x), int(y)) for x, y in zip(rng.integers(0, cam["width"], n_pixels), rng.integers(0, cam["height"], n_pixels))]
-    _CPU.update(sc=sc, v=v, window=window)
-    ctx = mp.get_context("fork")
     t1 = time.perf_counter()
     with ctx.Pool(workers) as pool:
         pool.map(_oracle_pixel, pix, chunksize=max(1, n_pixels // (4 * workers)))
     t_pix = time.perf_counter() - t1
-    px_per_s_full = n_pixels / t_pix / stride                # at the full Gaussian count
+    log(f"cpu baseline: {n_pixels} pixels in {t_pix:.1f} s")
     full = cam["width"] * cam["height"]
-    ms = (full / px_per_s_full + t_setup * stride) * 1e3
-    return {
-        "value": round(ms, 1),
-        "unit": "ms/iter (forward render only, extrapolated)",
-        "cores": workers,
-        "kind": "oracle",
-        "sample": f"every {stride}th Gaussian ({sc.n}) and {n_pixels} random pixels of the 1920x1080 frame, "
-                  f"float64 brute force; measured {n_pixels / t_pix:.2f} px/s and {t_setup:.1f} s setup on "
-                  f"{workers} processes, scaled x{stride} to the full Gaussian count and to the full frame; "
-                  f"no backward (the oracle's gradient is finite differences)",
-        "pixels_per_s_full_scene": round(px_per_s_full, 4),
-    }
+    ms = (t_setup + full * t_pix / n_pixels) * 1e3
+    res = {"value": round(ms, 1), "unit": "ms/iter (forward render only, extrapolated)", "cores": workers,
+           "kind": "oracle", "pixels_per_s": round(n_pixels / t_pix, 3),
+           "sample": f"render: camera view of all {n} Gaussians ({t_setup:.1f} s, chunked over {workers} processes) "
+                     f"and {n_pixels} random pixels of the 1920x1080 frame by float64 brute force over all of them "
+                     f"({n_pixels / t_pix:.2f} px/s on {workers} processes), extrapolated linearly to the {full} "
+                     f"pixels; no backward (the oracle's gradient is finite differences)"}
+    if qscene is None:
+        return res
+    # query sample
+    qcams_o = [O.Camera.from_arrays(**c) for c in qcams]
+    _CPU.update(qscene=qscene, qcams=qcams_o, qpts=np.asarray(qpts, np.float64))
+    nq = qscene["means"].shape[0]
+    t2 = time.perf_counter()
+    with ctx.Pool(workers) as pool:
+        prods = pool.map(_oracle_query_chunk, np.array_split(np.arange(nq), workers))
+    prod = np.prod(np.stack(prods), axis=0)
+    O_pts = [min([1.0] + [1.0 - prod[i, j] for j, c in enumerate(qcams_o) if O.point_view_valid(c, x)])
+             for i, x in enumerate(_CPU["qpts"])]
+    t_q = time.perf_counter() - t2
+    log(f"cpu baseline: {len(qpts)} query points in {t_q:.1f} s")
+    pts_per_s = len(qpts) / t_q
+    for k in ("scene", "sc", "v", "qscene", "qpts"):
+        _CPU.pop(k, None)
+    res["sample"] += (f"; query: {len(qpts)} of the points against all {nq} Gaussians and {len(qcams)} views "
+                      f"({t_q:.1f} s, the product over Gaussians split over {workers} processes), extrapolated to "
+                      f"all {n_query_total} points")
+    res["query_points_per_s"] = round(pts_per_s, 4)
+    res["query_ms_extrapolated"] = round(n_query_total / pts_per_s * 1e3, 1)
+    res["query_sample_opacity"] = [round(float(o), 7) for o in O_pts]
+    return res
 
 
 def per_view_query(qg, pts, qcams, tile, batched, t_batched, stream):
@@ -398,6 +557,9 @@ def window_sweep(g, C, capacity, target, d_acc, d_depth, d_normal, stream, steps
 
 def main():
     args = parse()
+    if args.summarize:
+        summarize(args)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU path is design-only.",
               file=sys.stderr)
@@ -406,13 +568,14 @@ def main():
     from paper_2506_19139_amd import scenes, sof
 
     torch.cuda.set_device(0)
-    if args.calib_copy_mib > 0:
-        n_el = args.calib_copy_mib * (1 << 20) // 4
-        src = torch.ones(n_el, device="cuda")
+    if args.calib_copy_mib > 0:                  # reference for the byte counters: a copy of known size
+        n4 = args.calib_copy_mib * (1 << 20) // 16
+        src = torch.ones(4 * n4, device="cuda")
         dst = torch.empty_like(src)
-        dst.copy_(src)
+        assert sof.lib().sof_bench_copy(sof._ptr(src), sof._ptr(dst), n4, sof._stream()) == 0
         torch.cuda.synchronize()
         del src, dst
+    peaks = None if args.no_peaks else sof.measure_peaks()
     log("scene: unbounded 1M")
     scene = scenes.unbounded_scene(args.n, seed=0)
     cam = scenes.circle_camera(0.0, 1920, 1080)
@@ -485,17 +648,30 @@ def main():
     dominant = "render_bwd" if kern["render_bwd"] >= kern["render_fwd"] else "render_fwd"
     flops = bwd_flops if dominant == "render_bwd" else fwd_flops
     achieved = flops / (kern[dominant] * 1e-3) / 1e12
-    roofline = {"bound": "alu", "kernel": f"k_{dominant}", "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS,
+    profile = read_profile()
+    dom_short = f"k_{dominant}<{args.tile}, {args.window}, false>"
+    cf = counter_figures(dom_short, args, profile)
+    roofline = {"bound": "alu", "kernel": dom_short, "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
-                "traffic": measured_traffic(f"k_{dominant}", args),
+                "traffic": (int(float(cf["read_bytes"]) + float(cf["write_bytes"])) if cf else None),
                 "hbm_frac": None,
                 "kernel_ms": round(kern[dominant], 4),
-                "valu_issue": measured_issue(f"k_{dominant}", args, kern[dominant]),
+                "valu_issue": None,
                 "work": {"entries_tested": int(walked), "candidates": int(cands), "blended": int(n_emit),
                          "flop": int(flops)}}
-
-    if roofline["traffic"]:                # measured HBM bytes over the kernel time, against 8 TB/s
+    if cf:                                 # counted HBM bytes over the live kernel time, against 8 TB/s
         roofline["hbm_frac"] = round(roofline["traffic"] / (kern[dominant] * 1e-3) / (HBM_PEAK_GBS * 1e9), 4)
+        issue_ms = float(cf["valu"]) * VALU_CYCLES / (N_SIMDS * CLOCK_GHZ * 1e9) * 1e3
+        roofline["valu_issue"] = {"valu_wave_insts": float(cf["valu"]), "issue_ms": round(issue_ms, 4),
+                                  "frac": round(issue_ms / kern[dominant], 3)}
+    if peaks:
+        roofline["measured_peaks"] = peaks
+        roofline["frac_of_measured_fma"] = round(achieved / peaks["fma_TFLOPs"], 4)
+    # every kernel of the step and the query with counter figures taken on its current sources
+    per_kernel = {k: {"us": float(r["avg_us"]), "bytes": int(float(r["read_bytes"]) + float(r["write_bytes"])),
+                      "hbm_frac": float(r["hbm_frac"]), "issue_frac": float(r["issue_frac"]),
+                      "lds_bank_conflict": float(r["lds_bank_conflict"])}
+                  for k, r in profile.items() if counter_figures(k, args, profile)}
 
     result = {
         "metric": METRIC,
@@ -515,6 +691,7 @@ def main():
                    "instances": int(k_used), "blended_per_pixel": round(n_emit / P, 2)},
         "per_call_ms": {k: round(v, 4) for k, v in per.items()},
         "roofline": roofline,
+        "per_kernel": {"source": os.path.relpath(PROFILE, ROOT), "kernels": per_kernel},
     }
 
     if not args.no_graph_step:
@@ -547,6 +724,8 @@ def main():
         qcams = sof.Cameras(scenes.ring_cameras(48, 960, 540))
         qg = sof.Gaussians.from_numpy(qscene)
         pts = torch.from_numpy(pts_np).cuda()
+        q_sample = np.random.default_rng(7).choice(pts_np.shape[0], args.cpu_query_points, replace=False)
+        q_sample_pts = pts_np[q_sample].copy()
         del pts_np
         q = sof.OpacityQuery(qcams, sof.Options(tile=args.query_tile))
         o = q(qg, pts)                                  # sizes the buffers (host read-back)
@@ -564,6 +743,8 @@ def main():
             times.append(a.elapsed_time(b))
         tq = float(np.median(times))
         tk = float(np.median(qtimer.ms("query")))
+        q_sample_gpu = o[torch.from_numpy(q_sample).cuda()].cpu().numpy()
+        n_query_points = int(pts.shape[0])
         npts = int(pts.shape[0])
         result["query"] = {"workload": f"{args.query_gaussians} Gaussians, {npts} points (centres + 3-sigma box "
                                        f"corners), min over {len(qcams)} views 960x540, one persistent launch",
@@ -590,10 +771,19 @@ def main():
             result["levelset"] = levelset_search(qg, pts, qcams, args.query_tile, tq, stream)
         del q, qg, pts, o
         torch.cuda.empty_cache()
+    else:
+        qscene = qcams = q_sample_pts = q_sample_gpu = None
+        n_query_points = 0
 
     if not args.no_cpu_baseline:
         log("cpu baseline")
-        result["cpu_baseline"] = cpu_baseline(scene, cam, args.window, args.cpu_pixels)
+        cb = cpu_baseline(scene, cam, args.window, args.cpu_pixels, qscene,
+                          None if qcams is None else qcams.list, q_sample_pts, n_query_points)
+        if q_sample_gpu is not None:           # the GPU's values of the same points beside the oracle's
+            cb["query_sample_gpu"] = [round(float(o), 7) for o in q_sample_gpu]
+            cb["query_sample_max_abs_diff"] = float(np.max(np.abs(np.asarray(cb["query_sample_opacity"]) -
+                                                                  q_sample_gpu)))
+        result["cpu_baseline"] = cb
 
     print(json.dumps(result), flush=True)
 

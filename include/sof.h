@@ -355,6 +355,18 @@ int sof_filter3d_bwd(const sof_gaussians* g, const float* var, const float* d_sc
 int sof_set_timing_events(void* const* events);
 
 /*
+ * Instrumentation, not part of the method: machine-peak probes for benchmarks.
+ *   sof_bench_copy  copies n_vec4 16-byte elements from src to dst (device, non-overlapping)
+ *                   with a grid-stride streaming kernel: reachable HBM bandwidth.
+ *   sof_bench_fma   runs n_blocks workgroups of 256 lanes, each lane 16 independent chains of
+ *                   `iters` float32 fused multiply-adds (2 x 16 x iters flops per lane), and
+ *                   writes one float per lane to out [n_blocks * 256]: reachable vector rate.
+ * Both return SOF_E_ARG for negative sizes or null buffers.
+ */
+int sof_bench_copy(const void* src, void* dst, int64_t n_vec4, hipStream_t stream);
+int sof_bench_fma(float* out, int64_t n_blocks, int32_t iters, hipStream_t stream);
+
+/*
  * sof_bisect_step -- one step of the binary search towards the 0.5 level set of the opacity
  * field (Sec. 3.4: eight steps on the edges of the tetrahedral grid).  a, b and mid are
  * device [n_edges, 3] float32 arrays: a[i] an endpoint inside (O > 0.5), b[i] one outside.

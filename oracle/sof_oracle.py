@@ -253,6 +253,18 @@ def view(scene: Scene, cam: Camera, appearance=True) -> CameraView:
                       gaussian_colors(scene, cam.center), gaussian_normals(scene, cam.center))
 
 
+def views_geometry(scene: Scene, cams):
+    """Geometry-only CameraViews of several cameras (what Eq. (12) reads), the world-space
+    precisions computed once and shared."""
+    prec = scene.precisions()
+    out = []
+    for cam in cams:
+        mu_c = scene.means @ cam.R.T + cam.t[None, :]
+        live = (scene.opac >= ALPHA_MIN) & (mu_c[:, 2] > NEAR)
+        out.append(CameraView(cam, live, prec, mu_c[:, 2].astype(np.float32), None, None))
+    return out
+
+
 # ----------------------------------------------------------------------------------------
 # Per-pixel candidates (Eq. (7)-(11))
 # ----------------------------------------------------------------------------------------

@@ -86,6 +86,8 @@ _SIGS = {
     "sof_filter3d_bwd": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P]),
     "sof_set_timing_events": (ctypes.c_int, [_P]),
     "sof_bisect_step": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int64, _P]),
+    "sof_bench_copy": (ctypes.c_int, [_P, _P, ctypes.c_int64, _P]),
+    "sof_bench_fma": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int32, _P]),
     "sof_strerror": (ctypes.c_char_p, [ctypes.c_int]),
 }
 
@@ -315,6 +317,35 @@ def read_status(buf: torch.Tensor):
     off = lib().sof_read_status_offset()
     raw = buf[off:off + 16].cpu().numpy()
     return int(raw[:8].view(np.int64)[0]), int(raw[8:12].view(np.int32)[0])
+
+
+def measure_peaks(copy_mib=2048, fma_blocks=256 * 64, fma_iters=4096, reps=5):
+    """Reachable machine peaks on the current device (instrumentation kernels of the library):
+    HBM GB/s of a streaming copy (bytes read + written) and float32 TFLOP/s of FMA chains,
+    each the best of `reps` timed launches after one warm-up."""
+    n4 = copy_mib * (1 << 20) // 16
+    src = torch.ones(4 * n4, device="cuda")
+    dst = torch.empty_like(src)
+    out = torch.empty(fma_blocks * 256, device="cuda")
+    s = _stream()
+
+    def best(fn):
+        fn()
+        ts = []
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            fn()
+            b.record()
+            torch.cuda.synchronize()
+            ts.append(a.elapsed_time(b))
+        return min(ts)
+    t_copy = best(lambda: _check(lib().sof_bench_copy(_ptr(src), _ptr(dst), n4, s), "sof_bench_copy"))
+    t_fma = best(lambda: _check(lib().sof_bench_fma(_ptr(out), fma_blocks, fma_iters, s), "sof_bench_fma"))
+    assert torch.equal(dst, src)
+    flops = 2.0 * 16 * fma_iters * fma_blocks * 256
+    return {"copy_GBps": round(2 * 16 * n4 / (t_copy * 1e-3) / 1e9, 1), "copy_bytes": 2 * 16 * n4,
+            "fma_TFLOPs": round(flops / (t_fma * 1e-3) / 1e12, 2), "fma_flops": int(flops)}
 
 
 TIMED_KERNELS = ("render_fwd", "render_bwd", "query")

@@ -196,7 +196,7 @@ def _check_directions(pairs, what):
         assert rel <= 1e-3, (what, groups, g, fd, rel)
 
 
-def _run_training_case(scene, cams, tile, window, pixels_per_cam, seed, label, opa=False):
+def _run_training_case(scene, cams, tile, window, pixels_per_cam, seed, label, opa=False, n_dirs=3):
     r = sof.Rasterizer(sof.Cameras(cams), sof.Options(tile=tile, window=window))
     g = sof.Gaussians.from_numpy(scene)
     out = r.forward(g, losses=opa)
@@ -224,7 +224,8 @@ def _run_training_case(scene, cams, tile, window, pixels_per_cam, seed, label, o
         assert float(np.abs(v[outside]).max(initial=0.0)) == 0.0, k
     # with the opacity term more decisions are piecewise constant (alpha at x against 1/255), so
     # its directions take a smaller step
-    pairs = _directional_fd(scene, cams, pixels_per_cam, weights, cam_ids, grads, window, seed=seed, opa=opa_terms,
+    pairs = _directional_fd(scene, cams, pixels_per_cam, weights, cam_ids, grads, window, n_dirs=n_dirs, seed=seed,
+                            opa=opa_terms,
                             lw=lw, h=1e-7 if opa else 1e-6)
     _check_directions(pairs, label)
 
@@ -294,18 +295,18 @@ def unbounded_1m():
 
 def test_unbounded_1m_1080p_training_step(unbounded_1m):
     """1M Gaussians (unbounded recipe, SH 3), 1920x1080, tile 16, window 8: the benchmark's
-    headline launch.  64 sampled pixels: forward parity and three directional derivatives."""
+    headline launch.  64 sampled pixels: forward parity and eight directional derivatives."""
     cam = scenes.circle_camera(0.0, 1920, 1080)
-    _run_training_case(unbounded_1m, [cam], 16, 8, [_sample_pixels(cam, 64, 1)], 21, "unbounded 1M 1080p")
+    _run_training_case(unbounded_1m, [cam], 16, 8, [_sample_pixels(cam, 64, 1)], 21, "unbounded 1M 1080p", n_dirs=8)
 
 
 def test_unbounded_1m_1080p_opacity_term(unbounded_1m):
     """The same launch with the opacity pass (L_opa) and the distortion and extent losses:
     their values on 64 sampled pixels and the directional derivatives of a loss that includes
-    them (the opacity's depth held at the oracle's)."""
+    them (the opacity's depth held at the oracle's); eight directional derivatives."""
     cam = scenes.circle_camera(0.0, 1920, 1080)
     _run_training_case(unbounded_1m, [cam], 16, 8, [_sample_pixels(cam, 64, 3)], 24, "unbounded 1M 1080p + L_opa",
-                       opa=True)
+                       opa=True, n_dirs=8)
 
 
 def test_unbounded_1m_eight_cameras_training_step(unbounded_1m):
