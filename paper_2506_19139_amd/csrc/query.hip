@@ -176,6 +176,8 @@ struct __align__(16) StageQ {
   float mz, o, thr, pad0;
   float m[9];
   float mu[3];
+  float pad1[4];        // 144-byte stride: the 16-byte stores of consecutive lanes when a batch is
+                        // staged start on 16 different LDS bank groups (128 bytes: only two)
 };
 
 struct QueryArgs {

@@ -39,31 +39,39 @@ __device__ inline float dpp_pull(float v) {
 }
 
 // Sum over the lanes where `mine` holds of 16 per-lane fields; every lane of the wave must be
-// active.  Inside each 16-lane row a reduce-scatter over four DPP stages halves the fields a
-// lane carries (the partner of each stage differs in one bit of the lane index: 3, 2, 1, 0),
-// leaving lane i with the row's total of field i; two cross-row exchanges then add the four
-// rows.  On return lane l holds the wave total of field (l & 15).
-__device__ inline float wave_field_sums16(const float* gv, bool mine, int lane) {
-  const int i = lane & 15;
-  const bool b3 = (i & 8) != 0, b2 = (i & 4) != 0, b1 = (i & 2) != 0, b0 = (i & 1) != 0;
-  float v8[8];
+// active.  A reduce-scatter that halves the fields a lane carries at each stage, starting with
+// the two cross-row exchanges of gfx950: a half-wave swap (lanes l and l ^ 32) adds field k
+// of the pair in the lower half and field k + 8 in the upper half with one swap and one add
+// per field pair, a swap of neighbouring rows (l and l ^ 16) does the same for the next bit,
+// then two DPP stages inside each row (partners i ^ 15 and i ^ 7: bits 3 and 2 differ) and two
+// plain quad sums.  On return lane l holds the wave total of field (l >> 2) & 15.
+__device__ inline float wave_field_sums16(const float* gv, bool mine) {
+  const int lane = (int)(threadIdx.x & 63);
+  const bool b3 = (lane & 8) != 0, b2 = (lane & 4) != 0;
+  float m[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) m[k] = mine ? gv[k] : 0.f;
+  // lanes l, l ^ 32: the first operand's upper half is swapped with the second's lower half
+  float s8[8];
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
-    const float lo = mine ? gv[k] : 0.f, hi = mine ? gv[k + 8] : 0.f;
-    v8[k] = (b3 ? hi : lo) + dpp_pull<kDppRowMirror>(b3 ? lo : hi);
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(m[k]), __float_as_uint(m[k + 8]), false, false);
+    s8[k] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
   }
-  float v4[4];
+  // lanes l, l ^ 16: odd rows of the first operand are swapped with even rows of the second
+  float s4[4];
 #pragma unroll
-  for (int k = 0; k < 4; ++k) v4[k] = (b2 ? v8[k + 4] : v8[k]) + dpp_pull<kDppRowHalfMirror>(b2 ? v8[k] : v8[k + 4]);
-  float v2[2];
+  for (int k = 0; k < 4; ++k) {
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(s8[k]), __float_as_uint(s8[k + 4]), false, false);
+    s4[k] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  }
+  float s2[2];
 #pragma unroll
-  for (int k = 0; k < 2; ++k) v2[k] = (b1 ? v4[k + 2] : v4[k]) + dpp_pull<kDppQuadXor2>(b1 ? v4[k] : v4[k + 2]);
-  float v1 = (b0 ? v2[1] : v2[0]) + dpp_pull<kDppQuadXor1>(b0 ? v2[0] : v2[1]);
-  // rows (0,1) and (2,3), then halves: each swap hands every lane its partner row's value
-  const auto r16 = __builtin_amdgcn_permlane16_swap(__float_as_uint(v1), __float_as_uint(v1), false, false);
-  v1 = __uint_as_float(r16[0]) + __uint_as_float(r16[1]);
-  const auto r32 = __builtin_amdgcn_permlane32_swap(__float_as_uint(v1), __float_as_uint(v1), false, false);
-  return __uint_as_float(r32[0]) + __uint_as_float(r32[1]);
+  for (int k = 0; k < 2; ++k) s2[k] = (b3 ? s4[k + 2] : s4[k]) + dpp_pull<kDppRowMirror>(b3 ? s4[k] : s4[k + 2]);
+  float s1 = (b2 ? s2[1] : s2[0]) + dpp_pull<kDppRowHalfMirror>(b2 ? s2[0] : s2[1]);
+  s1 += dpp_pull<kDppQuadXor2>(s1);
+  s1 += dpp_pull<kDppQuadXor1>(s1);
+  return s1;
 }
 
 // Five waves per SIMD (96 VGPRs; LDS allows five 256-lane workgroups per CU) hide more of the
@@ -386,7 +394,7 @@ __global__ __launch_bounds__(TS * TS, (TS >= 16 && W <= 8) ? (EXT ? 4 : 5) : 1) 
   // wave-cooperatively.  Lanes of one wave often hold the same instance (neighbouring
   // pixels share Gaussians), and float atomics to one LDS address serialise, so lanes are
   // grouped by instance: small groups add directly, a larger group is first summed across
-  // the wave (wave_field_sums16: each of 16 lanes ends with one field's total) and adds
+  // the wave (wave_field_sums16: each field total ends in one quad of lanes) and adds
   // once.  Entries older than the two resident batches add to the global buffer.
   auto round = [&](int cur_b) {
     float gv[kGradFields];
@@ -430,8 +438,8 @@ __global__ __launch_bounds__(TS * TS, (TS >= 16 && W <= 8) ? (EXT ? 4 : 5) : 1) 
       const uint32_t lp = __builtin_amdgcn_readlane(pos, leader);
       const bool mine = resident && pos == lp;           // the whole group is big
       big &= ~__ballot(mine);
-      const float v = wave_field_sums16(gv, mine, lane);
-      if (lane < kGradFields) atomicAdd(&gsl[((int)lp % NS) * kSlotStride + lane], v);
+      const float v = wave_field_sums16(gv, mine);
+      if ((lane & 3) == 0) atomicAdd(&gsl[((int)lp % NS) * kSlotStride + ((lane >> 2) & 15)], v);
     }
     has = false;
   };
