@@ -566,28 +566,68 @@ __global__ __launch_bounds__(kTileSortThreads) void k_tile_sort(const int2* rang
 }
 
 // Query tile lists with 32-bit keys: (tile << dbits) | quantised z_min, value = Gaussian id.
+// Wave-cooperative like k_emit: each wave owns 64 consecutive (camera, Gaussian) pairs and
+// writes their instances one per lane, so the stores are coalesced and no wave waits for the
+// largest rectangle among its lanes.
 __global__ __launch_bounds__(256) void k_emit_query32(const short4* rect, const float* zmin, int64_t n, int64_t vn,
                                                       int tile, const CamInfo* cams, const int32_t* counts,
                                                       const int64_t* offsets, int64_t cap, int dbits, uint32_t* keys,
                                                       uint32_t* vals, StatusBlock* status) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= vn) return;
-  const int cnt = counts[idx];
-  if (cnt == 0) return;
-  const short4 r = rect[idx];
-  const int c = (int)(idx / n);
-  const uint32_t g = (uint32_t)(idx - (int64_t)c * n);
-  const CamInfo ci = cams[c];
-  const uint32_t dk = query_depth_key(zmin[idx], query_key_shift(dbits));
-  int64_t e = offsets[idx];
-  if (e + cnt > cap) atomicOr(&status->flags, 1);
-  for (int ty = r.y / tile; ty <= r.w / tile; ++ty)
-    for (int tx = r.x / tile; tx <= r.z / tile; ++tx, ++e) {
-      if (e >= cap) return;
-      const uint32_t t = (uint32_t)(ci.tile_off + ty * ci.tiles_x + tx);
-      keys[e] = (t << dbits) | dk;
-      vals[e] = g;
+  __shared__ EmitOwner own[4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t base = ((int64_t)blockIdx.x * 4 + w) * 64;
+  if (base >= vn) return;                                 // wave-uniform
+  const int64_t vg = base + lane;
+  int cnt = 0;
+  if (vg < vn) {
+    cnt = counts[vg];
+    if (cnt > 0) {
+      const short4 r = rect[vg];
+      const int c = (int)(vg / n);
+      const CamInfo ci = cams[c];
+      EmitOwner o;
+      o.tx0 = r.x / tile;
+      o.ty0 = r.y / tile;
+      o.nx = r.z / tile - o.tx0 + 1;
+      o.toff = ci.tile_off;
+      o.tiles_x = ci.tiles_x;
+      o.g = (int32_t)(vg - (int64_t)c * n);
+      o.key = query_depth_key(zmin[vg], query_key_shift(dbits));
+      o.pad = 0;
+      own[w][lane] = o;
     }
+  }
+  int incl = cnt;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int y = __shfl_up(incl, d, 64);
+    if (lane >= d) incl += y;
+  }
+  const int total = __shfl(incl, 63, 64);
+  const int64_t e0 = offsets[base];
+  if (lane == 0 && e0 + total > cap && total > 0) atomicOr(&status->flags, 1);
+  __builtin_amdgcn_wave_barrier();
+  const int excl = incl - cnt;
+  for (int j0 = 0; j0 < total; j0 += 64) {
+    const int j = j0 + lane;
+    int lo = 0, hi = 63;
+#pragma unroll
+    for (int it = 0; it < 6; ++it) {
+      const int mid = (lo + hi) >> 1;
+      const bool right = __shfl(incl, mid, 64) <= j;
+      lo = right ? mid + 1 : lo;
+      hi = right ? hi : mid;
+    }
+    const int before = __shfl(excl, lo, 64);
+    const int64_t e = e0 + j;
+    if (j < total && e < cap) {
+      const EmitOwner o = own[w][lo];
+      const int local = j - before;
+      const uint32_t t = (uint32_t)(o.toff + (o.ty0 + local / o.nx) * o.tiles_x + (o.tx0 + local % o.nx));
+      keys[e] = (t << dbits) | o.key;
+      vals[e] = (uint32_t)o.g;
+    }
+  }
 }
 
 __global__ __launch_bounds__(256) void k_ranges32(const uint32_t* keys, const int64_t* count, int64_t cap, int dbits,
@@ -694,7 +734,7 @@ hipError_t launch_query_bin_sort(int64_t n, const sof_camera* d_cams, int n_cams
   hipError_t e = exclusive_scan<int32_t, int64_t>(counts, vn, offsets, scan_tmp, &status->count, s);
   if (e != hipSuccess) return e;
   if (vn > 0)
-    hipLaunchKernelGGL(k_emit_query32, dim3((unsigned)div_up(vn, th)), dim3(th), 0, s, rect, zmin, n, vn, tile, cams,
+    hipLaunchKernelGGL(k_emit_query32, dim3((unsigned)div_up(vn, 256)), dim3(256), 0, s, rect, zmin, n, vn, tile, cams,
                        counts, offsets, cap, dbits, k0, v0, status);
   e = radix_sort<uint32_t>(k0, v0, k1, v1, &status->count, cap, 32, hist, hist_tmp, parity, s);
   if (e != hipSuccess) return e;
