@@ -34,7 +34,9 @@ FP32_PEAK_TFLOPS = 157.3       # 256 CUs x 128 FP32 FMA lanes/clk (packed) x 2 x
 FLOP_EVAL = 23      # quadric of one (pixel, list entry): offsets, b', c', den', n', cut test
 FLOP_CAND = 9       # candidate: z test, reciprocal, exponent, alpha, key
 FLOP_BLEND = 15     # one blended Gaussian: transmittance, weight, colour and normal sums
-FLOP_ADJ = 110      # one replayed Gaussian in the backward: dalpha, chain to (mu_c, P_c), partials
+FLOP_ADJ = 110      # one blended Gaussian in the backward: dalpha, chain to (mu_c, P_c), partials
+# (the backward's own share of the candidate test and window is FLOP_EVAL / FLOP_CAND again
+# when it replays the order; with the order the forward recorded it has none)
 
 
 # Counter figures (HBM bytes, vector and LDS instructions) are taken with rocprofv3 over this
@@ -478,7 +480,7 @@ def opacity_term_step(g, C, opts, rast, out, grads, target, d_acc, d_depth, d_no
         sof.project(g, C, opts, rast.proj)
         sof.bin_sort(g.n, C, opts, rast.proj, rast.bins)
         sof.render_fwd(g.n, C, opts, rast.proj, rast.bins, out["rgb"], out["acc"], out["depth"], out["normal"],
-                       out["aux"], out["losses"])
+                       out["aux"], out["losses"], order=out["order"])
         if record: a[1].record(stream)
         opa = rast.opacity(g, out)
         if record: a[2].record(stream)
@@ -528,7 +530,8 @@ def window_sweep(g, C, capacity, target, d_acc, d_depth, d_normal, stream, steps
             if record: a[0].record(stream)
             sof.project(g, C, opts, r.proj)
             sof.bin_sort(g.n, C, opts, r.proj, r.bins)
-            sof.render_fwd(g.n, C, opts, r.proj, r.bins, o["rgb"], o["acc"], o["depth"], o["normal"], o["aux"])
+            sof.render_fwd(g.n, C, opts, r.proj, r.bins, o["rgb"], o["acc"], o["depth"], o["normal"], o["aux"],
+                           order=o["order"])
             d_rgb = torch.sign(o["rgb"] - target) * (1.0 / o["rgb"].numel())
             r.backward(g, o, d_rgb, d_acc, d_depth, d_normal, grads_out=gr)
             if record:
@@ -611,7 +614,7 @@ def main():
         sof.bin_sort(g.n, C, opts, rast.proj, rast.bins)
         if record: marks[2].record(stream)
         sof.render_fwd(g.n, C, opts, rast.proj, rast.bins, out["rgb"], out["acc"], out["depth"], out["normal"],
-                       out["aux"])
+                       out["aux"], order=out["order"])
         if record: marks[3].record(stream)
         d_rgb = torch.sign(out["rgb"] - target) * (1.0 / out["rgb"].numel())       # L1 loss gradient
         if record: marks[4].record(stream)
@@ -643,13 +646,18 @@ def main():
     n_emit = aux[1].view(torch.int32).double().sum().item()
     walked = aux[4].view(torch.int32).double().sum().item()
     cands = aux[5].view(torch.int32).double().sum().item()
+    recorded = out.get("order") is not None       # the backward reads the forward's order
     fwd_flops = FLOP_EVAL * walked + FLOP_CAND * cands + FLOP_BLEND * n_emit
-    bwd_flops = FLOP_EVAL * walked + FLOP_CAND * cands + FLOP_ADJ * n_emit
+    bwd_flops = FLOP_ADJ * n_emit + (0 if recorded else FLOP_EVAL * walked + FLOP_CAND * cands)
     dominant = "render_bwd" if kern["render_bwd"] >= kern["render_fwd"] else "render_fwd"
     flops = bwd_flops if dominant == "render_bwd" else fwd_flops
     achieved = flops / (kern[dominant] * 1e-3) / 1e12
     profile = read_profile()
-    dom_short = f"k_{dominant}<{args.tile}, {args.window}, false>"
+    if dominant == "render_bwd":
+        dom_short = (f"k_render_bwd<{args.tile}, 0, false, true>" if recorded
+                     else f"k_render_bwd<{args.tile}, {args.window}, false, false>")
+    else:
+        dom_short = f"k_render_fwd<{args.tile}, {args.window}, 0>"
     cf = counter_figures(dom_short, args, profile)
     roofline = {"bound": "alu", "kernel": dom_short, "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4),

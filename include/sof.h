@@ -110,20 +110,24 @@ typedef struct sof_options {
   float near_plane;          /* tau_n; the paper's near plane is 0.2                           */
   float bg[3];               /* background colour added with weight T_end (default 0)          */
   uint32_t flags;            /* SOF_* flags                                                    */
-  int32_t reserved;
+  int32_t order_slots;       /* 0..4096: Gaussians per pixel the recorded blend order holds
+                                (the `order` buffer of sof_render_fwd / sof_render_bwd); 0:
+                                no recorded order                                             */
   int64_t capacity;          /* maximum number of tile instances (all cameras), < 2^31         */
 } sof_options;
 
 /*
- * Sizes of the three caller-owned device buffers for a render of n Gaussians over the
- * given cameras:
+ * Sizes of the caller-owned device buffers for a render of n Gaussians over the given
+ * cameras:
  *   proj   per (camera, Gaussian) records written by sof_project          ~ 160 B x cams x n
  *   bins   tile instances, sort buffers, tile ranges, status word          ~ 24 B x capacity
  *   grads  per-instance gradient partials used only by sof_render_bwd      64 B x capacity
+ *   order  the recorded blend order (optional; 0 when opts->order_slots is 0): written by
+ *          sof_render_fwd, read by sof_render_bwd    2 B x order_slots x pixels (tile-padded)
  * Any output pointer may be NULL.  Returns SOF_E_ARG on invalid arguments.
  */
 int sof_workspace_size(int64_t n, const sof_camera* h_cams, int32_t n_cams, const sof_options* opts,
-                       size_t* proj_bytes, size_t* bins_bytes, size_t* grad_bytes);
+                       size_t* proj_bytes, size_t* bins_bytes, size_t* grad_bytes, size_t* order_bytes);
 
 /* Byte offset, inside `bins`, of the device status block:
  *   int64 [0] instance count K requested by the last sof_bin_sort (may exceed capacity)
@@ -187,11 +191,18 @@ int sof_bin_sort(int64_t n, const sof_camera* h_cams, const sof_camera* d_cams, 
  *                               output; alpha as in sof_render_opacity), channel 5 the position
  *                               of k in the blend order (int32, -1 without a crossing).  NULL:
  *                               not computed (a kernel without this work runs).
+ *   order  (optional, with aux; order_bytes from sof_workspace_size, opts->order_slots > 0)
+ *          the blend order of every pixel, for sof_render_bwd: per tile an int32 flag, then
+ *          per tile and 64-pixel wave (8x8 sub-tile) order_slots rows of 64 uint16 tile-list
+ *          positions, row e holding each pixel's e-th blended Gaussian.  A tile whose list is
+ *          longer than 2^16 or with a pixel that blends more than order_slots Gaussians is
+ *          flagged and its order is not used (the backward replays it).  Contents beyond
+ *          that are unspecified.  NULL: not recorded.
  */
 int sof_render_fwd(int64_t n, const sof_camera* h_cams, const sof_camera* d_cams, int32_t n_cams,
                    const sof_options* opts, const void* proj, size_t proj_bytes, const void* bins,
                    size_t bins_bytes, float* rgb, float* acc, float* depth, float* normal, float* aux,
-                   float* losses, hipStream_t stream);
+                   float* losses, void* order, size_t order_bytes, hipStream_t stream);
 
 /*
  * sof_render_order -- the per-pixel order of Sec. 3.1 (level-0 tile list, then the per-pixel
@@ -250,8 +261,10 @@ int sof_render_opacity(int64_t n, const sof_camera* h_cams, const sof_camera* d_
  * d_losses [2,H,W] (NULL = zero) is the upstream gradient of the forward's distortion and
  * extent losses; with it, losses is the forward's [4,H,W] losses output.  Their gradients
  * follow App. C.1 (dL/dalpha front to back from the stored totals) and C.2.
- * Each pixel's forward order is replayed front to back; suffix sums come from the stored
- * totals.  Writes (overwrites) d_means [n,3], d_scales [n,3], d_quats [n,4], d_opacities
+ * Each pixel's forward order is walked front to back; suffix sums come from the stored
+ * totals.  `order` (NULL or the forward's recorded order, with the same opts->order_slots)
+ * gives that order directly; without it, and for the tiles the forward flagged, the order is
+ * replayed (the same candidate test and window as the forward).  Writes (overwrites) d_means [n,3], d_scales [n,3], d_quats [n,4], d_opacities
  * [n], d_sh [n,K,3].  `grads` is scratch.  Reproducible to float rounding, not bitwise: a
  * tile's pixels add into each instance's partials with LDS float atomics, whose order follows
  * the scheduling of the tile's waves; the per-instance partials of a Gaussian are then summed
@@ -260,9 +273,10 @@ int sof_render_opacity(int64_t n, const sof_camera* h_cams, const sof_camera* d_
 int sof_render_bwd(const sof_gaussians* g, const sof_camera* h_cams, const sof_camera* d_cams,
                    int32_t n_cams, const sof_options* opts, const void* proj, size_t proj_bytes,
                    const void* bins, size_t bins_bytes, const float* rgb, const float* normal,
-                   const float* aux, const float* d_rgb, const float* d_acc, const float* d_depth,
-                   const float* d_normal, const float* depth, const float* opacity,
-                   const float* d_opacity, const float* losses, const float* d_losses, void* grads,
+                   const float* aux, const void* order, size_t order_bytes, const float* d_rgb,
+                   const float* d_acc, const float* d_depth, const float* d_normal, const float* depth,
+                   const float* opacity, const float* d_opacity, const float* losses,
+                   const float* d_losses, void* grads,
                    size_t grad_bytes, float* d_means, float* d_scales, float* d_quats,
                    float* d_opacities, float* d_sh, hipStream_t stream);
 
@@ -282,9 +296,10 @@ int sof_render_bwd(const sof_gaussians* g, const sof_camera* h_cams, const sof_c
 int sof_render_bwd_static(const sof_gaussians* g, const sof_camera* h_cams, const sof_camera* d_cams,
                           int32_t n_cams, const sof_options* opts, const void* proj, size_t proj_bytes,
                           const void* bins, size_t bins_bytes, const float* rgb, const float* normal,
-                          const float* aux, const float* d_rgb, const float* d_acc, const float* d_depth,
-                          const float* d_normal, const float* depth, const float* opacity,
-                          const float* d_opacity, const float* losses, const float* d_losses,
+                          const float* aux, const void* order, size_t order_bytes, const float* d_rgb,
+                          const float* d_acc, const float* d_depth, const float* d_normal,
+                          const float* depth, const float* opacity, const float* d_opacity,
+                          const float* losses, const float* d_losses,
                           float* d_means, float* d_scales, float* d_quats, float* d_opacities, float* d_sh,
                           hipStream_t stream);
 

@@ -27,6 +27,7 @@ int check_opts(const sof_options* o) {
   if (!render_supported(o->tile, o->window)) return SOF_E_UNSUPPORTED;
   if (!(o->near_plane > 0.f)) return SOF_E_ARG;
   if (o->capacity < 0 || o->capacity >= (int64_t(1) << 31)) return SOF_E_ARG;
+  if (o->order_slots < 0 || o->order_slots > kMaxOrderSlots) return SOF_E_ARG;
   return SOF_OK;
 }
 
@@ -111,7 +112,7 @@ const char* sof_strerror(int code) {
 }
 
 int sof_workspace_size(int64_t n, const sof_camera* h_cams, int32_t n_cams, const sof_options* opts,
-                       size_t* proj_bytes, size_t* bins_bytes, size_t* grad_bytes) {
+                       size_t* proj_bytes, size_t* bins_bytes, size_t* grad_bytes, size_t* order_bytes) {
   int st = check_opts(opts);
   if (st) return st;
   if (n < 0 || n >= (int64_t(1) << 31)) return SOF_E_ARG;
@@ -121,6 +122,7 @@ int sof_workspace_size(int64_t n, const sof_camera* h_cams, int32_t n_cams, cons
   if (proj_bytes) *proj_bytes = ProjLayout::make(vn).total;
   if (bins_bytes) *bins_bytes = BinsLayout::make(vn, n_cams, opts->capacity, n_tiles).total;
   if (grad_bytes) *grad_bytes = (size_t)opts->capacity * kGradFields * sizeof(float);
+  if (order_bytes) *order_bytes = opts->order_slots > 0 ? OrderLayout::make(n_tiles, opts->tile, opts->order_slots).total : 0;
   return SOF_OK;
 }
 
@@ -191,14 +193,34 @@ static int fill_fwd_args(int64_t n, const sof_camera* h_cams, const sof_camera* 
   return SOF_OK;
 }
 
+// The recorded blend order (null: none).  Needs opts->order_slots > 0 and a buffer of the
+// size sof_workspace_size gives.
+static int set_order(const sof_options* opts, int64_t n_tiles, const void* order, size_t order_bytes,
+                     RenderFwdArgs* a) {
+  a->order = nullptr;
+  a->order_flags = nullptr;
+  a->order_slots = 0;
+  if (!order) return SOF_OK;
+  if (opts->order_slots <= 0) return SOF_E_ARG;
+  const OrderLayout L = OrderLayout::make(n_tiles, opts->tile, opts->order_slots);
+  if (order_bytes < L.total) return SOF_E_WORKSPACE;
+  char* ob = (char*)order;
+  a->order_flags = (int32_t*)(ob + L.flags);
+  a->order = (uint16_t*)(ob + L.rec);
+  a->order_slots = opts->order_slots;
+  return SOF_OK;
+}
+
 int sof_render_fwd(int64_t n, const sof_camera* h_cams, const sof_camera* d_cams, int32_t n_cams,
                    const sof_options* opts, const void* proj, size_t proj_bytes, const void* bins, size_t bins_bytes,
                    float* rgb, float* acc, float* depth, float* normal, float* aux, float* losses,
-                   hipStream_t stream) {
+                   void* order, size_t order_bytes, hipStream_t stream) {
   RenderFwdArgs a;
   int64_t n_tiles = 0;
   int st = fill_fwd_args(n, h_cams, d_cams, n_cams, opts, proj, proj_bytes, bins, bins_bytes, &a, &n_tiles);
   if (st) return st;
+  if ((st = set_order(opts, n_tiles, order, order_bytes, &a))) return st;
+  if (a.order && !aux) return SOF_E_ARG;                // the backward reads both
   a.rgb = rgb; a.acc = acc; a.depth = depth; a.normal = normal; a.aux = aux; a.losses = losses;
   if (trace_enabled())
     fprintf(stderr, "[sof] render_fwd tiles=%lld tile=%d window=%d\n", (long long)n_tiles, opts->tile, opts->window);
@@ -272,17 +294,18 @@ int sof_render_opacity(int64_t n, const sof_camera* h_cams, const sof_camera* d_
 static int render_bwd_impl(const sof_gaussians* g, const sof_camera* h_cams, const sof_camera* d_cams,
                            int32_t n_cams, const sof_options* opts, const void* proj, size_t proj_bytes,
                            const void* bins, size_t bins_bytes, const float* rgb, const float* normal,
-                           const float* aux, const float* d_rgb, const float* d_acc, const float* d_depth,
-                           const float* d_normal, const float* depth, const float* opacity, const float* d_opacity,
-                           const float* losses, const float* d_losses, void* grads, size_t grad_bytes,
-                           float* d_means, float* d_scales, float* d_quats, float* d_opacities, float* d_sh,
-                           hipStream_t stream) {
+                           const float* aux, const void* order, size_t order_bytes, const float* d_rgb,
+                           const float* d_acc, const float* d_depth, const float* d_normal, const float* depth,
+                           const float* opacity, const float* d_opacity, const float* losses, const float* d_losses,
+                           void* grads, size_t grad_bytes, float* d_means, float* d_scales, float* d_quats,
+                           float* d_opacities, float* d_sh, hipStream_t stream) {
   int st = check_gauss(g, true);
   if (st) return st;
   RenderBwdArgs b;
   int64_t n_tiles = 0;
   st = fill_fwd_args(g->n, h_cams, d_cams, n_cams, opts, proj, proj_bytes, bins, bins_bytes, &b.f, &n_tiles);
   if (st) return st;
+  if ((st = set_order(opts, n_tiles, order, order_bytes, &b.f))) return st;
   if (!rgb || !aux) return SOF_E_ARG;
   if (d_normal && !normal) return SOF_E_ARG;            // its suffix sums need the forward's normal
   if (g->n > 0 && (!d_means || !d_scales || !d_quats || !d_opacities || !d_sh)) return SOF_E_ARG;
@@ -325,31 +348,33 @@ static int render_bwd_impl(const sof_gaussians* g, const sof_camera* h_cams, con
 
 int sof_render_bwd(const sof_gaussians* g, const sof_camera* h_cams, const sof_camera* d_cams, int32_t n_cams,
                    const sof_options* opts, const void* proj, size_t proj_bytes, const void* bins, size_t bins_bytes,
-                   const float* rgb, const float* normal, const float* aux, const float* d_rgb, const float* d_acc,
+                   const float* rgb, const float* normal, const float* aux, const void* order, size_t order_bytes,
+                   const float* d_rgb, const float* d_acc,
                    const float* d_depth, const float* d_normal, const float* depth, const float* opacity,
                    const float* d_opacity, const float* losses, const float* d_losses, void* grads,
                    size_t grad_bytes, float* d_means, float* d_scales, float* d_quats, float* d_opacities,
                    float* d_sh, hipStream_t stream) {
   return render_bwd_impl(g, h_cams, d_cams, n_cams, opts, proj, proj_bytes, bins, bins_bytes, rgb, normal, aux,
-                         d_rgb, d_acc, d_depth, d_normal, depth, opacity, d_opacity, losses, d_losses, grads,
-                         grad_bytes, d_means, d_scales, d_quats, d_opacities, d_sh, stream);
+                         order, order_bytes, d_rgb, d_acc, d_depth, d_normal, depth, opacity, d_opacity, losses,
+                         d_losses, grads, grad_bytes, d_means, d_scales, d_quats, d_opacities, d_sh, stream);
 }
 
 int sof_render_bwd_static(const sof_gaussians* g, const sof_camera* h_cams, const sof_camera* d_cams,
                           int32_t n_cams, const sof_options* opts, const void* proj, size_t proj_bytes,
                           const void* bins, size_t bins_bytes, const float* rgb, const float* normal,
-                          const float* aux, const float* d_rgb, const float* d_acc, const float* d_depth,
-                          const float* d_normal, const float* depth, const float* opacity, const float* d_opacity,
-                          const float* losses, const float* d_losses, float* d_means, float* d_scales,
-                          float* d_quats, float* d_opacities, float* d_sh, hipStream_t stream) {
+                          const float* aux, const void* order, size_t order_bytes, const float* d_rgb,
+                          const float* d_acc, const float* d_depth, const float* d_normal, const float* depth,
+                          const float* opacity, const float* d_opacity, const float* losses, const float* d_losses,
+                          float* d_means, float* d_scales, float* d_quats, float* d_opacities, float* d_sh,
+                          hipStream_t stream) {
   if (!opts) return SOF_E_ARG;
   if (opts->capacity > kStaticInstances) return SOF_E_SCRATCH;   // before any device call
   void* ptr = nullptr;
   const int st = static_scratch(&ptr);
   if (st) return st;
   return render_bwd_impl(g, h_cams, d_cams, n_cams, opts, proj, proj_bytes, bins, bins_bytes, rgb, normal, aux,
-                         d_rgb, d_acc, d_depth, d_normal, depth, opacity, d_opacity, losses, d_losses, ptr,
-                         sizeof(scratch), d_means, d_scales, d_quats, d_opacities, d_sh, stream);
+                         order, order_bytes, d_rgb, d_acc, d_depth, d_normal, depth, opacity, d_opacity, losses,
+                         d_losses, ptr, sizeof(scratch), d_means, d_scales, d_quats, d_opacities, d_sh, stream);
 }
 
 }  // extern "C"

@@ -58,8 +58,15 @@ struct RenderFwdArgs {
   float* depth;
   float* normal;
   float* aux;
-  float* losses;            // [4, P]: distortion, extent, sum w d, sum w d^2 (null: off)
+  float* losses;            // [6, P]: the loss outputs (null: off)
   OrderDump dump;
+  // Recorded blend order (null: not recorded).  The forward writes, for each pixel, the tile
+  // list position of every Gaussian it blends, in blend order, and one flag per tile; the
+  // backward then reads the order instead of replaying the candidate test and the window.
+  uint16_t* order;          // [tile][wave][slot][lane] (order_slots slots per pixel)
+  int32_t* order_flags;     // [tile] 1: not recorded (a pixel blends more than order_slots
+                            // Gaussians, or the tile list is longer than 2^16): replay it
+  int32_t order_slots;
 };
 
 struct RenderBwdArgs {

@@ -1,7 +1,9 @@
 // Backward rasteriser: the adjoint of render_fwd, without per-sample state.
 //
-// Each lane replays its pixel's forward order exactly (same staging, candidate test and
-// window code), recomputing the transmittance T_j front to back.  Contributions behind j
+// Each lane walks its pixel's forward order front to back: read from the order the forward
+// recorded (the list position of every blended Gaussian), or, without it and for the tiles
+// the forward could not record, replayed exactly (same staging, candidate test and window
+// code).  It recomputes the transmittance T_j on the way.  Contributions behind j
 // come from the stored totals: for F in {colour, normal}, dF/dalpha_j = T_j f_j -
 // (F_total - F_<=j) / (1 - alpha_j); d acc / d alpha_j = T_end / (1 - alpha_j).
 // The exact-depth correction (App. A.3) is either treated as a constant, as in the paper
@@ -21,11 +23,14 @@
 
 namespace sof {
 
+// Pending slots a lane may hold before a round is forced (see the emission loop).
+template <int W>
+constexpr int kPendingDepth = W >= 16 ? 1 : 4;
+
 struct PixBwd {
   float T;
   float S;                        // prefix sum of w (g_c . c + g_n . n)
-  int emitted, n_emit;
-  bool done, crossed;
+  bool crossed;
 };
 
 // Cross-lane read inside a row of 16 lanes (DPP, no LDS round trip).
@@ -78,13 +83,17 @@ __device__ inline float wave_field_sums16(const float* gv, bool mine) {
 // gather latency than four; the variant with the optional opacity and loss terms gets four.
 // Windows above 8 keep the default (their window registers would spill under either bound), and
 // so do 8x8 tiles, whose one-wave workgroups are held to three waves per SIMD by LDS.
-template <int TS, int W, bool EXT>
+//
+// LIST: the pixel's order is read from the forward's recorded order instead of being replayed
+// (no staging, candidate test or window); the kernel then runs on the tiles whose order was
+// recorded, the replay kernel on the others.
+template <int TS, int W, bool EXT, bool LIST>
 __global__ __launch_bounds__(TS * TS, (TS >= 16 && W <= 8) ? (EXT ? 4 : 5) : 1) void k_render_bwd(RenderBwdArgs A) {
   constexpr int NT = TS * TS;
-  constexpr int B = NT < 128 ? NT : 128;         // list entries staged per batch
+  constexpr int B = NT < 128 ? NT : 128;         // list entries per batch
   constexpr int NS = 2 * B;                      // resident gradient slots (two batches)
-  __shared__ StageEntry stage[B];
-  __shared__ uint2 srect[B];
+  __shared__ StageEntry stage[LIST ? 1 : B];
+  __shared__ uint2 srect[LIST ? 1 : B];
   constexpr int kSlotStride = kGradFields + 1;   // padded: fields of one slot and equal fields
                                                  // of neighbouring slots fall in distinct banks
   constexpr int kGroupReduce = 4;                // lanes sharing an instance: reduce first
@@ -92,6 +101,9 @@ __global__ __launch_bounds__(TS * TS, (TS >= 16 && W <= 8) ? (EXT ? 4 : 5) : 1) 
   __shared__ uint2 ring[NS];                     // (emission index, Gaussian) of each resident list slot
   const RenderFwdArgs& a = A.f;
   const int tile = blockIdx.x;
+  if (a.order) {
+    if (LIST == (a.order_flags[tile] != 0)) return;   // the other kernel's tile
+  }
   const int c = find_cam(a.cam_info, a.n_cams, tile);
   const CamInfo ci = a.cam_info[c];
   const sof_camera& cam = a.cams[c];
@@ -199,21 +211,37 @@ __global__ __launch_bounds__(TS * TS, (TS >= 16 && W <= 8) ? (EXT ? 4 : 5) : 1) 
 
   PixBwd p;
   p.T = 1.f; p.S = 0.f;
-  p.emitted = 0; p.n_emit = n_emit; p.crossed = false;
-  p.done = !inside || n_emit == 0;
+  p.crossed = false;
   Window<W> win;
   win.init();
 
-  // Emission, in the forward's order.  The window holds (key, list slot) only: when an entry
-  // leaves it the lane marks the slot pending, and once per list step every lane with a
-  // pending slot gathers the Gaussian, recomputes its alpha (bit-identical to the candidate
-  // test: same pixel offset, quadric terms, reciprocal and exp2), advances the transmittance
-  // and prefix sums and forms all partials.  The partials are then added wave-cooperatively,
-  // so lanes holding the same Gaussian can be summed across the wave before touching LDS.
-  bool has = false;
-  uint32_t qpos = 0u;            // pending list slot
+  // Emission, in the forward's order.  The window holds (key, list slot) only: an entry that
+  // leaves it is queued in a short per-lane FIFO of pending slots.  A round takes the oldest
+  // pending slot of every lane that has one: it gathers the Gaussian, recomputes its alpha
+  // (bit-identical to the candidate test: same pixel offset, quadric terms, reciprocal and
+  // exp2), advances the transmittance and prefix sums and forms all partials, which are then
+  // added wave-cooperatively, so lanes holding the same Gaussian are summed across the wave
+  // before touching LDS.  A round costs the same whatever number of lanes take part, so rounds
+  // are deferred until every lane that can still emit has a pending slot, or one lane's FIFO
+  // is full; each lane still handles its slots in emission order.
+  constexpr int D = kPendingDepth<W>;
+  uint32_t fifo[D];              // pending list slots, oldest first
+#pragma unroll
+  for (int i = 0; i < D; ++i) fifo[i] = 0u;
+  int nq = 0;                    // pending count
+  int n_out = 0;                 // slots emitted so far (queued or done)
+  bool has = false;              // this round's slot (fifo head) and its lane
+  uint32_t qpos = 0u;
   uint32_t qe = 0u;              // its instance (emission index)
   int32_t qg = 0;                // and Gaussian (stale on lanes without a pending slot)
+  auto queue = [&](uint32_t pos) {
+#pragma unroll
+    for (int i = 0; i < D; ++i) fifo[i] = nq == i ? pos : fifo[i];
+    ++nq;
+    ++n_out;
+  };
+  // the forward blended n_emit entries; the lane emits no more once that many have left
+  auto emit_done = [&]() { return n_out >= n_emit; };
 
   // Gaussian of list slot `pos`: from the LDS ring while its batch is resident
   auto slot_gaussian = [&](uint32_t pos, int cur_b, uint32_t& e) -> int32_t {
@@ -271,7 +299,6 @@ __global__ __launch_bounds__(TS * TS, (TS >= 16 && W <= 8) ? (EXT ? 4 : 5) : 1) 
       p.S = S;
       p.T = testT;
       if (is_k) p.crossed = true;
-      if (++p.emitted >= p.n_emit) p.done = true;
     }
 
     // ---- chain rule to (mu_c, P_c)
@@ -441,7 +468,26 @@ __global__ __launch_bounds__(TS * TS, (TS >= 16 && W <= 8) ? (EXT ? 4 : 5) : 1) 
       const float v = wave_field_sums16(gv, mine);
       if ((lane & 3) == 0) atomicAdd(&gsl[((int)lp % NS) * kSlotStride + ((lane >> 2) & 15)], v);
     }
-    has = false;
+  };
+  // the oldest pending slot of each lane is this round's
+  auto take_head = [&]() {
+    has = nq > 0;
+    qpos = fifo[0];
+#pragma unroll
+    for (int i = 0; i < D - 1; ++i) fifo[i] = fifo[i + 1];
+    nq = has ? nq - 1 : 0;
+  };
+  // after a list step: a round once every lane that can still emit has a pending slot, or when
+  // a FIFO is full (the next step may queue one more).  Deeper FIFOs measured slower (depth 6:
+  // 3.29 -> 3.46 ms at 1M Gaussians 1080p), and so did a 3/4 quorum (3.33 ms)
+  auto maybe_round = [&](int cur_b) {
+    const uint64_t pend = __ballot(nq > 0);
+    if (!pend) return;
+    const uint64_t act = __ballot(nq > 0 || !emit_done());
+    if (__any(nq >= D) || pend == act) {
+      take_head();
+      round(cur_b);
+    }
   };
 
   // write the resident slots of batch b to the per-instance buffer and clear them
@@ -461,57 +507,95 @@ __global__ __launch_bounds__(TS * TS, (TS >= 16 && W <= 8) ? (EXT ? 4 : 5) : 1) 
   };
 
   int cur_b = -1;
-  for (int bs = rg.x; bs < rg.y; bs += B) {
-    if (__syncthreads_count(!p.done) == 0) break;       // window contents are drained after the loop
-    ++cur_b;
-    flush(cur_b - 2);
-    const int i = bs + (int)threadIdx.x;
-    if (threadIdx.x < B && i < rg.y) {
-      const uint32_t e = A.f.vals[i];
-      const int32_t g = A.f.gid[e];
-      stage_entry(a.geom, a.rect, cam_base + g, x0, y0, (uint32_t)(i - rg.x), &stage[threadIdx.x],
-                  &srect[threadIdx.x]);
-      ring[(i - rg.x) % NS] = make_uint2(e, (uint32_t)g);
+  if constexpr (LIST) {
+    // this lane's recorded order: row e of the wave's rows is its e-th blended Gaussian.  Each
+    // batch takes the lane's next entries in blend order while their list position lies in
+    // the batches staged so far (a Gaussian leaves the window at or after its own position),
+    // so the slots of the last two batches stay resident as in the replay
+    const uint16_t* recw =
+        a.order + ((int64_t)tile * (NT / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6)) * a.order_slots * 64 +
+        (threadIdx.x & 63);
+    // (the forward flags a tile with more than order_slots blended Gaussians in a pixel, so
+    // n_rec = n_emit here; the bounds only keep inconsistent inputs inside the buffers)
+    const int n_rec = min(n_emit, a.order_slots);
+    int kd = 0;                                           // entries taken
+    uint32_t nxt = n_rec > 0 ? (uint32_t)recw[0] : 0xFFFFFFFFu;
+    for (int bs = rg.x; bs < rg.y; bs += B) {
+      if (__syncthreads_count(kd < n_rec) == 0) break;
+      ++cur_b;
+      flush(cur_b - 2);
+      const int i = bs + (int)threadIdx.x;
+      if (threadIdx.x < B && i < rg.y) {
+        const uint32_t e = A.f.vals[i];
+        ring[(i - rg.x) % NS] = make_uint2(e, (uint32_t)A.f.gid[e]);
+      }
+      __builtin_amdgcn_s_waitcnt(0x0F70);               // vmcnt(0): see the replay below
+      __syncthreads();
+      const uint32_t lim = (uint32_t)min((cur_b + 1) * B, len);
+      while (true) {
+        const bool go = kd < n_rec && nxt < lim;
+        if (!__any(go)) break;
+        has = go;
+        qpos = nxt;
+        if (go) {
+          ++kd;
+          nxt = kd < n_rec ? (uint32_t)recw[(int64_t)kd * 64] : 0xFFFFFFFFu;
+        }
+        round(cur_b);
+      }
     }
-    // The flushed slots and any later global atomics on them (entries emitted after their
-    // batch left the ring) come from this workgroup only: waiting until this lane's stores
-    // are acknowledged by L2 and then the barrier order them, without the L2 write-back and
-    // invalidation of a device-scope fence.
-    __builtin_amdgcn_s_waitcnt(0x0F70);                 // vmcnt(0)
-    __syncthreads();
-    const int nb = min(B, rg.y - bs);
-    for (int j = 0; j < nb; ++j) {
-      if (!__any(!p.done)) break;
-      if (misses_subtile(uniform_rect(srect[j]), sxu, syu)) continue;      // wave-uniform
-      const StageEntry e = stage[j];
-      const Cand1 c1 = candidate_stage1(e, lx, ly, near_plane);
-      if (!__any(c1.pre && !p.done)) continue;
-      float key, al;
-      const bool cand = candidate_stage2(e, c1, key, al) && !p.done;
-      if (__any(cand)) {
-        if (cand) {
+  } else {
+    for (int bs = rg.x; bs < rg.y; bs += B) {
+      if (__syncthreads_count(!emit_done()) == 0) break;  // window and FIFO are drained after the loop
+      ++cur_b;
+      flush(cur_b - 2);
+      const int i = bs + (int)threadIdx.x;
+      if (threadIdx.x < B && i < rg.y) {
+        const uint32_t e = A.f.vals[i];
+        const int32_t g = A.f.gid[e];
+        stage_entry(a.geom, a.rect, cam_base + g, x0, y0, (uint32_t)(i - rg.x), &stage[threadIdx.x],
+                    &srect[threadIdx.x]);
+        ring[(i - rg.x) % NS] = make_uint2(e, (uint32_t)g);
+      }
+      // The flushed slots and any later global atomics on them (entries emitted after their
+      // batch left the ring) come from this workgroup only: waiting until this lane's stores
+      // are acknowledged by L2 and then the barrier order them, without the L2 write-back and
+      // invalidation of a device-scope fence.
+      __builtin_amdgcn_s_waitcnt(0x0F70);                 // vmcnt(0)
+      __syncthreads();
+      const int nb = min(B, rg.y - bs);
+      for (int j = 0; j < nb; ++j) {
+        // a wave whose lanes have all emitted their count finishes its FIFOs after the list
+        if (!__any(!emit_done())) break;
+        if (misses_subtile(uniform_rect(srect[j]), sxu, syu)) continue;      // wave-uniform
+        const StageEntry e = stage[j];
+        const Cand1 c1 = candidate_stage1(e, lx, ly, near_plane);
+        if (!__any(c1.pre && !emit_done())) continue;
+        float key, al;
+        const bool cand = candidate_stage2(e, c1, key, al) && !emit_done();
+        if (__any(cand)) {
+          if (cand) {
+            float ea;
+            uint32_t et;
+            // alpha is recomputed on emission, so the window carries none (its moves fold away)
+            if (win.push(key, 0.f, __float_as_uint(e.tag), ea, et)) queue(et);
+          }
+          maybe_round(cur_b);
+        }
+      }
+    }
+    // the rest of the window (in order) behind the pending slots: one new slot per lane and round
+    while (__any(nq > 0 || (W > 0 && !emit_done() && win.count > 0))) {
+      if constexpr (W > 0) {
+        if (!emit_done() && win.count > 0 && nq < D) {
           float ea;
           uint32_t et;
-          // alpha is recomputed on emission, so the window carries none (its moves fold away)
-          if (win.push(key, 0.f, __float_as_uint(e.tag), ea, et)) {
-            has = true;
-            qpos = et;
-          }
+          win.pop_front(ea, et);
+          queue(et);
         }
-        if (__any(has)) round(cur_b);
       }
-    }
-  }
-  if constexpr (W > 0) {
-    while (__any(!p.done && win.count > 0)) {
-      if (!p.done && win.count > 0) {
-        float ea;
-        uint32_t et;
-        win.pop_front(ea, et);
-        has = true;
-        qpos = et;
-      }
-      if (__any(has)) round(cur_b);
+      take_head();
+      round(cur_b);
     }
   }
   __syncthreads();
@@ -525,17 +609,24 @@ __global__ __launch_bounds__(TS * TS, (TS >= 16 && W <= 8) ? (EXT ? 4 : 5) : 1) 
   }
 }
 
+// With a recorded order: the order-reading kernel over the recorded tiles, then the replay
+// over the flagged ones (each kernel leaves the other's tiles at once; they share no instance).
 template <int TS, bool EXT>
 static hipError_t launch_bwd_tso(const RenderBwdArgs& a, int window, int64_t n_tiles, hipStream_t s) {
   const dim3 grid((unsigned)n_tiles), block(TS * TS);
+  if (a.f.order) {
+    hipLaunchKernelGGL((k_render_bwd<TS, 0, EXT, true>), grid, block, 0, s, a);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   switch (window) {
-    case 0: hipLaunchKernelGGL((k_render_bwd<TS, 0, EXT>), grid, block, 0, s, a); break;
-    case 1: hipLaunchKernelGGL((k_render_bwd<TS, 1, EXT>), grid, block, 0, s, a); break;
-    case 2: hipLaunchKernelGGL((k_render_bwd<TS, 2, EXT>), grid, block, 0, s, a); break;
-    case 4: hipLaunchKernelGGL((k_render_bwd<TS, 4, EXT>), grid, block, 0, s, a); break;
-    case 8: hipLaunchKernelGGL((k_render_bwd<TS, 8, EXT>), grid, block, 0, s, a); break;
-    case 16: hipLaunchKernelGGL((k_render_bwd<TS, 16, EXT>), grid, block, 0, s, a); break;
-    case 32: hipLaunchKernelGGL((k_render_bwd<TS, 32, EXT>), grid, block, 0, s, a); break;
+    case 0: hipLaunchKernelGGL((k_render_bwd<TS, 0, EXT, false>), grid, block, 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_render_bwd<TS, 1, EXT, false>), grid, block, 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_render_bwd<TS, 2, EXT, false>), grid, block, 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_render_bwd<TS, 4, EXT, false>), grid, block, 0, s, a); break;
+    case 8: hipLaunchKernelGGL((k_render_bwd<TS, 8, EXT, false>), grid, block, 0, s, a); break;
+    case 16: hipLaunchKernelGGL((k_render_bwd<TS, 16, EXT, false>), grid, block, 0, s, a); break;
+    case 32: hipLaunchKernelGGL((k_render_bwd<TS, 32, EXT, false>), grid, block, 0, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

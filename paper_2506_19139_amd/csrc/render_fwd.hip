@@ -1,11 +1,12 @@
 // Forward rasteriser: one workgroup per screen tile (TS x TS lanes, one pixel per lane).
-// The tile's list is staged through LDS in batches of TS*TS entries with one coalesced
+// The tile's list is staged through LDS in batches of up to 128 entries with one coalesced
 // 64-byte record load per lane; every lane then walks the batch from LDS (broadcast reads),
 // tests candidates, feeds its register window and blends what the window emits front to
 // back (Eq. (1)).  The workgroup leaves the list once no lane is still accumulating.
 // Outputs per pixel: colour, accumulated opacity, exact depth (Sec. 3.2), normal, the
 // replay state the backward pass needs and two work counters (list entries tested,
-// candidates that passed the alpha cut).
+// candidates that passed the alpha cut); optionally the blend order itself (the list
+// position of every blended Gaussian), which spares the backward the replay.
 #include "render_common.h"
 
 namespace sof {
@@ -32,16 +33,15 @@ __device__ inline float crossing_depth(const float4& r3, const Quad& q, float Tk
   return dn * (sstar - sqrtf(L / A));
 }
 
-// Returns the blend weight (0 when the Gaussian was not blended).
-__device__ inline float blend(PixFwd& p, float alpha, uint32_t gid, const float4* app, int64_t cam_base) {
+// Blends Gaussian `gid` with colour c and normal nn; returns the blend weight (0 when the
+// Gaussian was not blended).
+__device__ inline float blend(PixFwd& p, float alpha, uint32_t gid, const float4& c, const float4& nn) {
   const float test_T = p.T * (1.f - alpha);
   if (test_T < kTMin) {
     p.done = true;
     return 0.f;
   }
   const float w = alpha * p.T;
-  const float4 c = app[2 * (cam_base + gid)];
-  const float4 nn = app[2 * (cam_base + gid) + 1];
   p.r = fmaf(w, c.x, p.r);
   p.g = fmaf(w, c.y, p.g);
   p.b = fmaf(w, c.z, p.b);
@@ -162,19 +162,27 @@ __device__ inline void write_pixel(const RenderFwdArgs& a, const PixFwd& p, cons
 // with stores added, so its decisions are those of the plain forward).
 enum FwdMode { kFwdPlain = 0, kFwdLoss = 1, kFwdDump = 2 };
 
-// Seven waves per SIMD (72 VGPRs) measure faster than the six the register count would give
-// for windows up to 8, and five (96 VGPRs) than four for a window of 16 (1.90 -> 1.74 ms at
-// 1080p); a window of 32 and the variants with the loss moments or the order output keep
-// the default.
+// Six waves per SIMD (80 VGPRs) for windows up to 8: seven (72 VGPRs) spill the blend
+// accumulators (1.81 vs 1.25 ms at 1080p), five measure 1.33 ms; four (128 VGPRs) for a
+// window of 16 (no spills).  8x8 tiles (held by LDS to four one-wave workgroups per SIMD), a
+// window of 32 and the variants with the loss moments or the order output keep the default.
 template <int TS, int W, int MODE>
-__global__ __launch_bounds__(TS * TS, MODE != kFwdPlain ? 1 : (W <= 8 ? 7 : (W == 16 ? 5 : 1))) void k_render_fwd(
-    RenderFwdArgs a) {
+__global__ __launch_bounds__(TS * TS, (MODE != kFwdPlain || TS < 16) ? 1 : (W <= 8 ? 6 : (W == 16 ? 4 : 1)))
+    void k_render_fwd(RenderFwdArgs a) {
   constexpr bool LOSS = MODE == kFwdLoss;
   constexpr bool DUMP = MODE == kFwdDump;
+  // the window's tag: the entry's list position, from which the recorded order is written,
+  // except in the order output, which reports Gaussian indices.  With positions, the Gaussian
+  // index, colour and normal of the last two batches' entries are kept in LDS rings, so that
+  // a blend reads them there (an older entry, rare, is looked up in the list and gathered)
+  constexpr bool POS = !DUMP;
   constexpr int NT = TS * TS;
-  constexpr int B = NT < 256 ? NT : 256;         // list entries staged per batch
+  constexpr int B = NT < 128 ? NT : 128;         // list entries staged per batch
+  constexpr int NR = POS ? 2 * B : 1;            // ring entries
   __shared__ StageEntry stage[B];
   __shared__ uint2 srect[B];
+  __shared__ int32_t gring[NR];
+  __shared__ float4 aring[2 * NR];               // colour, normal
   const int tile = blockIdx.x;
   const int c = find_cam(a.cam_info, a.n_cams, tile);
   const CamInfo ci = a.cam_info[c];
@@ -237,12 +245,65 @@ __global__ __launch_bounds__(TS * TS, MODE != kFwdPlain ? 1 : (W <= 8 ? 7 : (W =
     }
   };
 
+  // recorded order: this wave's rows (row e = each lane's e-th blended Gaussian; a
+  // wave-uniform base, the lane's column added at the store)
+  uint16_t* recw = nullptr;
+  if constexpr (POS) {
+    if (a.order)
+      recw = a.order + ((int64_t)tile * (NT / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6)) * a.order_slots * 64;
+  }
+  int cur_b = -1;
+  // blend the entry that left the window (tag et, alpha ea, key ek)
+  // (its Gaussian: the tag itself, or for a list position the ring entry of the last two
+  // batches or, for an older entry, the list)
+  auto emit = [&](uint32_t et, float ea, float ek) {
+    record_out(et);
+    uint32_t g = et;
+    float4 cc, nn;
+    if constexpr (POS) {
+      const int r = (int)(et % NR);
+      uint32_t g0 = (uint32_t)gring[r];
+      float4 c0 = aring[2 * r], n0 = aring[2 * r + 1];
+      // (the empty asm keeps the LDS reads here: sunk into the blend branch, they would merge
+      // with the global reads below into generic loads)
+      __asm__ volatile("" : "+v"(g0), "+v"(c0.x), "+v"(c0.y), "+v"(c0.z), "+v"(n0.x), "+v"(n0.y), "+v"(n0.z));
+      if ((int)et < (cur_b - 1) * B) {
+        g0 = (uint32_t)a.gid[a.vals[rg.x + (int)et]];
+        c0 = a.app[2 * (cam_base + g0)];
+        n0 = a.app[2 * (cam_base + g0) + 1];
+      }
+      g = g0;
+      cc = c0;
+      nn = n0;
+    } else {
+      cc = a.app[2 * (cam_base + g)];
+      nn = a.app[2 * (cam_base + g) + 1];
+    }
+    const int k_before = p.k, n_before = p.n_emit;
+    const float w = blend(p, ea, g, cc, nn);
+    if constexpr (POS) {
+      if (recw && p.n_emit > n_before && n_before < a.order_slots)
+        recw[n_before * 64 + (int)(threadIdx.x & 63)] = (uint16_t)et;
+    }
+    if constexpr (LOSS) {
+      if (w > 0.f) loss_terms(p, w, ek, g, a.geom, cam_base, px, py, dn, k_before < 0 && p.k >= 0, a.flags, near_plane);
+    }
+  };
+
   for (int bs = rg.x; bs < rg.y; bs += B) {
     if (__syncthreads_count(!p.done) == 0) break;
+    ++cur_b;
     const int i = bs + (int)threadIdx.x;
     if (threadIdx.x < B && i < rg.y) {
       const int32_t g = a.gid[a.vals[i]];
-      stage_entry(a.geom, a.rect, cam_base + g, x0, y0, (uint32_t)g, &stage[threadIdx.x], &srect[threadIdx.x]);
+      stage_entry(a.geom, a.rect, cam_base + g, x0, y0, POS ? (uint32_t)(i - rg.x) : (uint32_t)g, &stage[threadIdx.x],
+                  &srect[threadIdx.x]);
+      if constexpr (POS) {
+        const int r = (i - rg.x) % NR;
+        gring[r] = g;
+        aring[2 * r] = a.app[2 * (cam_base + g)];
+        aring[2 * r + 1] = a.app[2 * (cam_base + g) + 1];
+      }
     }
     __syncthreads();
     const int nb = min(B, rg.y - bs);
@@ -261,14 +322,7 @@ __global__ __launch_bounds__(TS * TS, MODE != kFwdPlain ? 1 : (W <= 8 ? 7 : (W =
         float ea, ek;
         uint32_t et;
         record_fed(__float_as_uint(e.tag), key);
-        if (win.push(key, al, __float_as_uint(e.tag), ea, et, ek)) {
-          record_out(et);
-          const int k_before = p.k;
-          const float w = blend(p, ea, et, a.app, cam_base);
-          if constexpr (LOSS) {
-            if (w > 0.f) loss_terms(p, w, ek, et, a.geom, cam_base, px, py, dn, k_before < 0 && p.k >= 0, a.flags, near_plane);
-          }
-        }
+        if (win.push(key, al, __float_as_uint(e.tag), ea, et, ek)) emit(et, ea, ek);
       }
     }
   }
@@ -277,12 +331,13 @@ __global__ __launch_bounds__(TS * TS, MODE != kFwdPlain ? 1 : (W <= 8 ? 7 : (W =
       float ea, ek;
       uint32_t et;
       win.pop_front(ea, et, ek);
-      record_out(et);
-      const int k_before = p.k;
-      const float w = blend(p, ea, et, a.app, cam_base);
-      if constexpr (LOSS) {
-        if (w > 0.f) loss_terms(p, w, ek, et, a.geom, cam_base, px, py, dn, k_before < 0 && p.k >= 0, a.flags, near_plane);
-      }
+      emit(et, ea, ek);
+    }
+  }
+  if constexpr (POS) {
+    if (a.order) {
+      const int over = __syncthreads_or(p.n_emit > a.order_slots);
+      if (threadIdx.x == 0) a.order_flags[tile] = (over || rg.y - rg.x > kMaxOrderListLength) ? 1 : 0;
     }
   }
   if (!inside) return;

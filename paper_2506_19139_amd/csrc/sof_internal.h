@@ -119,6 +119,23 @@ struct BinsLayout {
   }
 };
 
+// Recorded blend order (sof_render_fwd writes it, sof_render_bwd reads it): one int32 flag
+// per tile, then for each tile and 64-lane wave `slots` rows of 64 uint16 list positions
+// (row e holds each lane's e-th blended Gaussian), so that a wave's reads and writes of one
+// row are one contiguous 128-byte segment.
+constexpr int64_t kMaxOrderSlots = 4096;
+constexpr int64_t kMaxOrderListLength = 65536;  // positions are stored in 16 bits
+struct OrderLayout {
+  size_t flags, rec, total;
+  static __host__ __device__ OrderLayout make(int64_t n_tiles, int tile, int64_t slots) {
+    OrderLayout L;
+    L.flags = 0;
+    L.rec = align_up((size_t)(n_tiles > 0 ? n_tiles : 1) * 4);
+    L.total = L.rec + (size_t)n_tiles * tile * tile * slots * 2;
+    return L;
+  }
+};
+
 // Number of bits needed to hold values 0..v-1 (at least 1).
 inline __host__ __device__ int bits_for(int64_t v) {
   int b = 1;

@@ -29,6 +29,9 @@ SOF_QUERY_REUSE = 1 << 4
 WINDOWS = (0, 1, 2, 4, 8, 16, 32)
 AUX_CHANNELS = 6      # T_end, n_emitted, k, T_k, entries tested, candidates
 LOSS_CHANNELS = 6     # distortion, extent, mean and moment of d, opacity tail, position of k
+# Gaussians per pixel the recorded blend order holds by default; a tile with a pixel that blends
+# more is replayed by the backward instead (at 1M Gaussians and 1080p the most is ~150)
+DEFAULT_ORDER_SLOTS = 256
 TILES = (8, 16, 32)
 
 
@@ -50,7 +53,7 @@ class CCamera(ctypes.Structure):
 
 class COptions(ctypes.Structure):
     _fields_ = [("tile", ctypes.c_int32), ("window", ctypes.c_int32), ("near_plane", ctypes.c_float),
-                ("bg", ctypes.c_float * 3), ("flags", ctypes.c_uint32), ("reserved", ctypes.c_int32),
+                ("bg", ctypes.c_float * 3), ("flags", ctypes.c_uint32), ("order_slots", ctypes.c_int32),
                 ("capacity", ctypes.c_int64)]
 
 
@@ -61,23 +64,23 @@ _P = ctypes.c_void_p
 _SZ = ctypes.POINTER(ctypes.c_size_t)
 
 _SIGS = {
-    "sof_workspace_size": (ctypes.c_int, [ctypes.c_int64, _P, ctypes.c_int32, _P, _SZ, _SZ, _SZ]),
+    "sof_workspace_size": (ctypes.c_int, [ctypes.c_int64, _P, ctypes.c_int32, _P, _SZ, _SZ, _SZ, _SZ]),
     "sof_read_status_offset": (ctypes.c_size_t, []),
     "sof_project": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, _P, _P, ctypes.c_size_t, _P]),
     "sof_bin_sort": (ctypes.c_int, [ctypes.c_int64, _P, _P, ctypes.c_int32, _P, _P, ctypes.c_size_t, _P,
                                     ctypes.c_size_t, _P]),
     "sof_render_fwd": (ctypes.c_int, [ctypes.c_int64, _P, _P, ctypes.c_int32, _P, _P, ctypes.c_size_t, _P,
-                                      ctypes.c_size_t, _P, _P, _P, _P, _P, _P, _P]),
+                                      ctypes.c_size_t, _P, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]),
     "sof_render_order": (ctypes.c_int, [ctypes.c_int64, _P, _P, ctypes.c_int32, _P, _P, ctypes.c_size_t, _P,
                                         ctypes.c_size_t, _P, ctypes.c_int64, ctypes.c_int32, _P, _P, _P, _P, _P]),
     "sof_render_opacity": (ctypes.c_int, [ctypes.c_int64, _P, _P, ctypes.c_int32, _P, _P, ctypes.c_size_t, _P,
                                           ctypes.c_size_t, _P, _P, _P, _P, _P]),
     "sof_render_bwd": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, _P, _P, ctypes.c_size_t, _P, ctypes.c_size_t,
-                                      _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P, _P,
-                                      _P, _P, _P, _P]),
+                                      _P, _P, _P, _P, ctypes.c_size_t, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
+                                      ctypes.c_size_t, _P, _P, _P, _P, _P, _P]),
     "sof_render_bwd_static": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, _P, _P, ctypes.c_size_t, _P,
-                                             ctypes.c_size_t, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
-                                             _P, _P, _P, _P, _P, _P]),
+                                             ctypes.c_size_t, _P, _P, _P, _P, ctypes.c_size_t, _P, _P, _P, _P, _P,
+                                             _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "sof_query_workspace_size": (ctypes.c_int, [ctypes.c_int64, _P, ctypes.c_int32, _P, ctypes.c_int64,
                                                 ctypes.c_int64, _SZ, _SZ, _SZ]),
     "sof_opacity_query": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, _P, _P, ctypes.c_int64, ctypes.c_int64,
@@ -119,6 +122,10 @@ def _ptr(t):
     if t is None:
         return None
     return ctypes.c_void_p(t.data_ptr())
+
+
+def _nbytes(t):
+    return 0 if t is None else t.numel() * t.element_size()
 
 
 def _stream():
@@ -199,23 +206,26 @@ class Options:
     bg: tuple = (0.0, 0.0, 0.0)
     flags: int = 0
     capacity: int = 0
+    # per-pixel capacity of the recorded blend order (0: none; the backward then replays)
+    order_slots: int = DEFAULT_ORDER_SLOTS
 
     def c_struct(self):
         o = COptions()
         o.tile, o.window, o.near_plane = int(self.tile), int(self.window), float(self.near_plane)
         o.bg[:] = [float(x) for x in self.bg]
-        o.flags, o.reserved, o.capacity = int(self.flags), 0, int(self.capacity)
+        o.flags, o.order_slots, o.capacity = int(self.flags), int(self.order_slots), int(self.capacity)
         return o
 
 
 # ------------------------------------------------------------------------------ raw calls
 
 def workspace_size(n, cams: Cameras, opts: Options):
-    p, b, g = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
+    """(proj, bins, grads, order) buffer sizes in bytes."""
+    p, b, g, r = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
     o = opts.c_struct()
     _check(lib().sof_workspace_size(n, cams.hp(), len(cams), ctypes.byref(o), ctypes.byref(p), ctypes.byref(b),
-                                    ctypes.byref(g)), "sof_workspace_size")
-    return p.value, b.value, g.value
+                                    ctypes.byref(g), ctypes.byref(r)), "sof_workspace_size")
+    return p.value, b.value, g.value, r.value
 
 
 def project(g: Gaussians, cams: Cameras, opts: Options, proj: torch.Tensor):
@@ -231,11 +241,11 @@ def bin_sort(n, cams: Cameras, opts: Options, proj, bins):
 
 
 def render_fwd(n, cams: Cameras, opts: Options, proj, bins, rgb=None, acc=None, depth=None, normal=None, aux=None,
-               losses=None):
+               losses=None, order=None):
     o = opts.c_struct()
     _check(lib().sof_render_fwd(n, cams.hp(), cams.dp(), len(cams), ctypes.byref(o), _ptr(proj), proj.numel(),
                                 _ptr(bins), bins.numel(), _ptr(rgb), _ptr(acc), _ptr(depth), _ptr(normal), _ptr(aux),
-                                _ptr(losses), _stream()), "sof_render_fwd")
+                                _ptr(losses), _ptr(order), _nbytes(order), _stream()), "sof_render_fwd")
 
 
 def render_order(n, cams: Cameras, opts: Options, proj, bins, slot, n_slots, max_entries):
@@ -265,11 +275,11 @@ def render_opacity(n, cams: Cameras, opts: Options, proj, bins, depth, aux, opac
 
 def render_bwd(g: Gaussians, cams: Cameras, opts: Options, proj, bins, rgb, normal, aux, d_rgb, d_acc, d_depth,
                d_normal, grads, d_means, d_scales, d_quats, d_opac, d_sh, depth=None, opacity=None, d_opacity=None,
-               losses=None, d_losses=None):
+               losses=None, d_losses=None, order=None):
     gs, o = g.c_struct(), opts.c_struct()
     _check(lib().sof_render_bwd(ctypes.byref(gs), cams.hp(), cams.dp(), len(cams), ctypes.byref(o), _ptr(proj),
                                 proj.numel(), _ptr(bins), bins.numel(), _ptr(rgb), _ptr(normal), _ptr(aux),
-                                _ptr(d_rgb), _ptr(d_acc), _ptr(d_depth), _ptr(d_normal), _ptr(depth), _ptr(opacity),
+                                _ptr(order), _nbytes(order), _ptr(d_rgb), _ptr(d_acc), _ptr(d_depth), _ptr(d_normal), _ptr(depth), _ptr(opacity),
                                 _ptr(d_opacity), _ptr(losses), _ptr(d_losses), _ptr(grads),
                                 grads.numel() if grads is not None else 0,
                                 _ptr(d_means), _ptr(d_scales), _ptr(d_quats), _ptr(d_opac), _ptr(d_sh), _stream()),
@@ -278,13 +288,13 @@ def render_bwd(g: Gaussians, cams: Cameras, opts: Options, proj, bins, rgb, norm
 
 def render_bwd_static(g: Gaussians, cams: Cameras, opts: Options, proj, bins, rgb, normal, aux, d_rgb, d_acc,
                       d_depth, d_normal, d_means, d_scales, d_quats, d_opac, d_sh, depth=None, opacity=None,
-                      d_opacity=None, losses=None, d_losses=None):
+                      d_opacity=None, losses=None, d_losses=None, order=None):
     """sof_render_bwd_static: the backward without a caller workspace (the library's static
     per-device scratch holds the per-instance partials; opts.capacity <= 2^20)."""
     gs, o = g.c_struct(), opts.c_struct()
     _check(lib().sof_render_bwd_static(ctypes.byref(gs), cams.hp(), cams.dp(), len(cams), ctypes.byref(o),
                                        _ptr(proj), proj.numel(), _ptr(bins), bins.numel(), _ptr(rgb), _ptr(normal),
-                                       _ptr(aux), _ptr(d_rgb), _ptr(d_acc), _ptr(d_depth), _ptr(d_normal),
+                                       _ptr(aux), _ptr(order), _nbytes(order), _ptr(d_rgb), _ptr(d_acc), _ptr(d_depth), _ptr(d_normal),
                                        _ptr(depth), _ptr(opacity), _ptr(d_opacity), _ptr(losses), _ptr(d_losses),
                                        _ptr(d_means), _ptr(d_scales), _ptr(d_quats), _ptr(d_opac), _ptr(d_sh),
                                        _stream()), "sof_render_bwd_static")
@@ -399,6 +409,18 @@ def sorted_instances(bins: torch.Tensor, n, cams: Cameras, opts: Options):
     return keys, ids, ranges
 
 
+def recorded_order(order: torch.Tensor, cams: Cameras, opts: Options):
+    """Debug view of the recorded blend order (synchronises): (flags [n_tiles] int32,
+    positions [n_tiles, TS*TS/64, order_slots, 64] uint16) as numpy arrays."""
+    T = opts.tile
+    n_tiles = sum(((w + T - 1) // T) * ((h + T - 1) // T) for w, h in cams.sizes)
+    b = order.cpu().numpy()
+    rec = _align(4 * max(n_tiles, 1))
+    flags = b[:4 * n_tiles].view(np.int32)
+    pos = b[rec:rec + 2 * n_tiles * T * T * opts.order_slots].view(np.uint16)
+    return flags, pos.reshape(n_tiles, T * T // 64, opts.order_slots, 64)
+
+
 def proj_view(proj: torch.Tensor, n, n_cams):
     """Debug view of sof_project's per (camera, Gaussian) records as numpy arrays
     (synchronises): rect [V*N,4] int16, mu_z [V*N] float32, zmin [V*N] float32."""
@@ -444,7 +466,7 @@ class Rasterizer:
     def __init__(self, cams: Cameras, opts: Options, auto_capacity=True, device="cuda"):
         self.cams, self.opts, self.device = cams, opts, device
         self.auto_capacity = auto_capacity
-        self.proj = self.bins = self.grads = None
+        self.proj = self.bins = self.grads = self.order_rec = None
         self._n = -1
         self.last_count = 0
         # bumped by every prepare(): proj and bins then hold another frame's lists, so a
@@ -452,13 +474,17 @@ class Rasterizer:
         self.generation = 0
 
     def _alloc(self, n):
-        p, b, g = workspace_size(n, self.cams, self.opts)
+        p, b, g, r = workspace_size(n, self.cams, self.opts)
         if self.proj is None or self.proj.numel() < p:
             self.proj = torch.empty(p, dtype=torch.uint8, device=self.device)
         if self.bins is None or self.bins.numel() < b:
             self.bins = torch.empty(b, dtype=torch.uint8, device=self.device)
         if self.grads is None or self.grads.numel() < g:
             self.grads = torch.empty(max(g, 16), dtype=torch.uint8, device=self.device)
+        if r == 0:
+            self.order_rec = None
+        elif self.order_rec is None or self.order_rec.numel() < r:
+            self.order_rec = torch.empty(r, dtype=torch.uint8, device=self.device)
 
     def prepare(self, g: Gaussians):
         """project + bin_sort; returns the instance count (read back only in auto mode)."""
@@ -481,18 +507,24 @@ class Rasterizer:
     def alloc_outputs(self):
         P = self.cams.n_pixels
         dev = self.device
+        # "order" is the rasterizer's own recorded-order buffer (None until allocated or when
+        # opts.order_slots is 0): a forward writes it, the backward of that forward reads it
         return dict(rgb=torch.empty(3 * P, device=dev), acc=torch.empty(P, device=dev), depth=torch.empty(P, device=dev),
-                    normal=torch.empty(3 * P, device=dev), aux=torch.empty(AUX_CHANNELS * P, device=dev))
+                    normal=torch.empty(3 * P, device=dev), aux=torch.empty(AUX_CHANNELS * P, device=dev),
+                    order=self.order_rec)
 
     def forward(self, g: Gaussians, out=None, losses=False):
         """Render; with losses=True also the per-pixel distortion and extent losses in
-        out["losses"] ([4, P]: distortion, extent, and two sums the backward reads)."""
+        out["losses"] ([6, P]: distortion, extent, and four channels the backward and the
+        opacity pass read).  With opts.order_slots > 0 the blend order is recorded into the
+        rasterizer's order buffer (out["order"]) for the backward."""
         self.prepare(g)
         out = out or self.alloc_outputs()
         if losses and "losses" not in out:
             out["losses"] = torch.empty(LOSS_CHANNELS * self.cams.n_pixels, device=self.device)
+        out["order"] = self.order_rec
         render_fwd(g.n, self.cams, self.opts, self.proj, self.bins, out["rgb"], out["acc"], out["depth"],
-                   out["normal"], out["aux"], out["losses"] if losses else None)
+                   out["normal"], out["aux"], out["losses"] if losses else None, order=out["order"])
         return out
 
     def order(self, g: Gaussians, pixels_per_cam, max_entries=512):
@@ -547,7 +579,8 @@ class Rasterizer:
                    d_depth, d_normal, self.grads, grads_out["means"], grads_out["scales"], grads_out["quats"],
                    grads_out["opac"], grads_out["sh"], depth=out["depth"] if d_opa is not None else None,
                    opacity=out.get("opa") if d_opa is not None else None, d_opacity=d_opa,
-                   losses=out.get("losses") if d_losses is not None else None, d_losses=d_losses)
+                   losses=out.get("losses") if d_losses is not None else None, d_losses=d_losses,
+                   order=out.get("order"))
         return grads_out
 
     def split(self, flat, channels):
@@ -573,6 +606,7 @@ class SofRasterize(torch.autograd.Function):
         # the backward replays from the rasterizer's proj / bins buffers: remember which
         # frame they hold, so that a later forward through the same rasterizer is caught
         ctx.rast, ctx.generation, ctx.sh_degree = rast, rast.generation, int(sh_degree)
+        ctx.order = out["order"]          # the rasterizer's buffer, guarded by the generation
         ctx.save_for_backward(g.means, g.scales, g.quats, g.opac, g.sh, out["rgb"], out["normal"], out["aux"])
         return out["rgb"], out["acc"], out["depth"], out["normal"]
 
@@ -583,7 +617,7 @@ class SofRasterize(torch.autograd.Function):
                            "(its tile lists were overwritten); use one Rasterizer per pending backward")
         means, scales, quats, opac, sh, rgb, normal, aux = ctx.saved_tensors
         g = Gaussians(means, scales, quats, opac, sh, ctx.sh_degree)
-        out = dict(rgb=rgb, normal=normal, aux=aux)
+        out = dict(rgb=rgb, normal=normal, aux=aux, order=ctx.order)
         c = lambda t: None if t is None else t.contiguous()
         gr = ctx.rast.backward(g, out, c(d_rgb), c(d_acc), c(d_depth), c(d_normal))
         return gr["means"], gr["scales"], gr["quats"], gr["opac"], gr["sh"], None, None

@@ -40,7 +40,7 @@ class TrainStep:
         sof.project(self.g, self.cams, self.opts, r.proj)
         sof.bin_sort(self.g.n, self.cams, self.opts, r.proj, r.bins)
         sof.render_fwd(self.g.n, self.cams, self.opts, r.proj, r.bins, o["rgb"], o["acc"], o["depth"], o["normal"],
-                       o["aux"])
+                       o["aux"], order=o["order"])
         torch.sign(o["rgb"] - self.target, out=self.d_rgb)
         self.d_rgb.mul_(1.0 / self.d_rgb.numel())                         # d(mean |rgb - target|)
         r.backward(self.g, o, self.d_rgb, self.extra.get("acc"), self.extra.get("depth"), self.extra.get("normal"),

@@ -120,7 +120,7 @@ def test_capacity_overflow_writes_nothing_out_of_bounds():
     g = sof.Gaussians.from_numpy(scene)
     C = sof.Cameras([cam])
     opts = sof.Options(tile=16, window=8, capacity=100)
-    pb, bb, gb = sof.workspace_size(g.n, C, opts)
+    pb, bb, gb, ob = sof.workspace_size(g.n, C, opts)
     GUARD = 1 << 16
 
     def guarded(nbytes):
@@ -129,6 +129,7 @@ def test_capacity_overflow_writes_nothing_out_of_bounds():
     proj_all, proj = guarded(pb)
     bins_all, bins = guarded(bb)
     grads_all, grads = guarded(gb)
+    order_all, order = guarded(ob)
     P = C.n_pixels
     outs = {k: guarded(4 * c * P) for k, c in (("rgb", 3), ("acc", 1), ("depth", 1), ("normal", 3),
                                                 ("aux", sof.AUX_CHANNELS))}
@@ -136,14 +137,16 @@ def test_capacity_overflow_writes_nothing_out_of_bounds():
     print("[case] capacity 100 with guard regions", flush=True)
     sof.project(g, C, opts, proj)
     sof.bin_sort(g.n, C, opts, proj, bins)
-    sof.render_fwd(g.n, C, opts, proj, bins, view["rgb"], view["acc"], view["depth"], view["normal"], view["aux"])
+    sof.render_fwd(g.n, C, opts, proj, bins, view["rgb"], view["acc"], view["depth"], view["normal"], view["aux"],
+                   order=order)
     d = [torch.empty_like(t) for t in (g.means, g.scales, g.quats, g.opac, g.sh)]
     sof.render_bwd(g, C, opts, proj, bins, view["rgb"], view["normal"], view["aux"], torch.ones_like(view["rgb"]),
-                   None, None, None, grads, *d)
+                   None, None, None, grads, *d, order=order)
     torch.cuda.synchronize()
     k, flags = sof.read_status(bins)
     assert k > 100 and (flags & 1) == 1
-    for name, (full, used) in [("proj", (proj_all, proj)), ("bins", (bins_all, bins)), ("grads", (grads_all, grads))] + \
+    for name, (full, used) in [("proj", (proj_all, proj)), ("bins", (bins_all, bins)), ("grads", (grads_all, grads)),
+                               ("order", (order_all, order))] + \
             [(k_, v) for k_, v in outs.items()]:
         tail = full[used.numel():].cpu().numpy()
         assert np.all(tail == 0xA5), name

@@ -1,0 +1,154 @@
+"""The recorded blend order: sof_render_fwd writes each pixel's blended Gaussians (their tile
+list positions, in blend order) and sof_render_bwd walks that order instead of replaying the
+candidate test and the resort window (Sec. 3.1 order, adjoint of Eq. (1)).
+
+Checks: the recorded order equals the order output of sof_render_order entry by entry; the
+backward from the recorded order equals the replaying backward (the same partials, added in
+another grouping: float rounding only); tiles the forward cannot record (a pixel with more
+blended Gaussians than the per-pixel slots, a tile list longer than 2^16) are flagged and
+replayed; recording changes none of the forward's outputs."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2506_19139_amd import scenes, sof
+
+pytestmark = pytest.mark.gpu
+
+
+def _render(scene, cam, tile, window, order_slots=sof.DEFAULT_ORDER_SLOTS, flags=0, losses=False):
+    g = sof.Gaussians.from_numpy(scene)
+    C = sof.Cameras([cam])
+    opts = sof.Options(tile=tile, window=window, flags=flags, order_slots=order_slots)
+    r = sof.Rasterizer(C, opts)
+    out = r.forward(g, losses=losses)
+    torch.cuda.synchronize()
+    return r, g, C, opts, out
+
+
+def _decode(r, g, C, opts, out, cam):
+    """Per pixel (row-major), the recorded Gaussian ids; per tile, the flag."""
+    flags, pos = sof.recorded_order(out["order"], C, opts)
+    _, ids, ranges = sof.sorted_instances(r.bins, g.n, C, opts)
+    T = opts.tile
+    W, H = cam["width"], cam["height"]
+    tiles_x = (W + T - 1) // T
+    n_emit = out["aux"].view(sof.AUX_CHANNELS, H, W)[1].cpu().numpy().view(np.int32)
+    res = {}
+    for py in range(H):
+        for px in range(W):
+            t = (py // T) * tiles_x + px // T
+            if flags[t]:
+                continue
+            lx, ly = px % T, py % T
+            w = (ly // 8) * (T // 8) + lx // 8
+            lane = (ly % 8) * 8 + lx % 8
+            p = pos[t, w, :n_emit[py, px], lane].astype(np.int64)
+            res[(px, py)] = ids[ranges[t, 0] + p]
+    return flags, res, n_emit
+
+
+@pytest.mark.parametrize("window", [0, 4, 8, 16, 32])
+def test_recorded_order_is_the_blend_order(window):
+    scene, cam = scenes.small_scene(), scenes.small_camera()
+    for tile in (8, 16, 32):
+        print(f"[case] recorded order, small scene tile {tile} window {window}", flush=True)
+        r, g, C, opts, out = _render(scene, cam, tile, window)
+        flags, rec, n_emit = _decode(r, g, C, opts, out, cam)
+        assert not flags.any()
+        pixels = [(x, y) for y in range(cam["height"]) for x in range(cam["width"])]
+        dump = r.order(g, [pixels])[0]
+        for (px, py), d in zip(pixels, dump):
+            n = n_emit[py, px]
+            # the order output also lists the entry whose alpha ended the pixel unblended
+            assert np.array_equal(rec[(px, py)], d["emit_ids"][:n]), (px, py)
+
+
+def test_recording_changes_no_forward_output():
+    scene, cam = scenes.small_scene(), scenes.small_camera()
+    a = _render(scene, cam, 16, 8)[4]
+    b = _render(scene, cam, 16, 8, order_slots=0)[4]
+    assert b["order"] is None
+    for k in ("rgb", "acc", "depth", "normal", "aux"):
+        assert torch.equal(a[k].view(torch.int32), b[k].view(torch.int32)), k
+
+
+def _upstream(C, seed, out=None, losses=False, opacity=False):
+    P = C.n_pixels
+    gen = torch.Generator(device="cuda").manual_seed(seed)
+    ups = dict(d_rgb=torch.randn(3 * P, device="cuda", generator=gen) / P,
+               d_acc=torch.randn(P, device="cuda", generator=gen) / P,
+               d_depth=torch.randn(P, device="cuda", generator=gen) / P,
+               d_normal=torch.randn(3 * P, device="cuda", generator=gen) / P)
+    if losses:
+        ups["d_losses"] = torch.randn(2 * P, device="cuda", generator=gen) / P
+    if opacity:
+        ups["d_opa"] = torch.randn(P, device="cuda", generator=gen) / P
+    return ups
+
+
+def _backward_both(r, g, out, ups):
+    """The backward from the recorded order and the replaying one (same forward)."""
+    rec = r.backward(g, out, **ups)
+    rec = {k: v.clone() for k, v in rec.items()}
+    rep = r.backward(g, {**out, "order": None}, **ups)
+    torch.cuda.synchronize()
+    return rec, rep
+
+
+def _same(rec, rep, tol=1e-5):
+    for k in ("means", "scales", "quats", "opac", "sh"):
+        a, b = rec[k].cpu().numpy(), rep[k].cpu().numpy()
+        assert np.all(np.isfinite(a)), k
+        scale = max(float(np.abs(b).max()), 1e-30)
+        err = float(np.abs(a - b).max()) / scale
+        print(f"  {k}: max |recorded - replayed| / max |replayed| = {err:.2e}")
+        assert err <= tol, (k, err)
+
+
+@pytest.mark.parametrize("tile,window", [(8, 8), (16, 0), (16, 8), (16, 16), (32, 4)])
+def test_backward_from_the_recorded_order_equals_the_replay(tile, window):
+    scene, cam = scenes.small_scene(), scenes.small_camera()
+    print(f"[case] backward recorded vs replayed tile {tile} window {window}", flush=True)
+    r, g, C, opts, out = _render(scene, cam, tile, window)
+    _same(*_backward_both(r, g, out, _upstream(C, 3)))
+
+
+@pytest.mark.parametrize("full_depth", [False, True])
+def test_backward_with_losses_and_opacity_from_the_recorded_order(full_depth):
+    scene, cam = scenes.small_scene(), scenes.small_camera()
+    flags = sof.SOF_DEPTH_GRAD_FULL if full_depth else 0
+    print(f"[case] backward with losses and opacity, recorded vs replayed, full depth {full_depth}", flush=True)
+    r, g, C, opts, out = _render(scene, cam, 16, 8, flags=flags, losses=True)
+    r.opacity(g, out)
+    _same(*_backward_both(r, g, out, _upstream(C, 4, losses=True, opacity=True)))
+
+
+def test_tiles_with_more_blended_gaussians_than_slots_are_replayed():
+    scene, cam = scenes.small_scene(), scenes.small_camera()
+    slots = 12
+    print(f"[case] {slots} order slots: some tiles flagged", flush=True)
+    r, g, C, opts, out = _render(scene, cam, 8, 8, order_slots=slots)
+    flags, _, n_emit = _decode(r, g, C, opts, out, cam)
+    H, W = n_emit.shape
+    over = n_emit.reshape(H // 8, 8, W // 8, 8).max(axis=(1, 3)).reshape(-1) > slots
+    print(f"  {over.sum()} of {over.size} tiles flagged")
+    assert 0 < over.sum() < over.size
+    assert np.array_equal(flags != 0, over)
+    _same(*_backward_both(r, g, out, _upstream(C, 5)))
+
+
+def test_a_tile_list_longer_than_two_to_the_sixteen_is_replayed():
+    """70,000 small Gaussians in front of an 8x8 image (one tile): the tile list is too long for
+    16-bit positions."""
+    cam = scenes.small_camera(8, 8)
+    scene = scenes.small_scene(70_000, seed=9)
+    print("[case] tile list of 70,000 entries", flush=True)
+    r, g, C, opts, out = _render(scene, cam, 8, 8, order_slots=4096)     # no pixel fills the slots
+    _, _, ranges = sof.sorted_instances(r.bins, g.n, C, opts)
+    flags, _, n_emit = _decode(r, g, C, opts, out, cam)
+    longest = int((ranges[:, 1] - ranges[:, 0]).max())
+    print(f"  longest list {longest}, most blended {n_emit.max()}")
+    assert longest > 65536 and n_emit.max() <= opts.order_slots
+    assert flags.all()
+    _same(*_backward_both(r, g, out, _upstream(C, 6)))

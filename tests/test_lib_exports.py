@@ -39,18 +39,28 @@ def test_host_argument_checks():
     cam = (sof.CCamera * 1)()
     cam[0].fx = cam[0].fy = 50.0
     cam[0].width, cam[0].height = 64, 48
-    p, b, g = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
-    o = sof.Options(tile=16, window=8, capacity=1000).c_struct()
+    p, b, g, r = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
+    o = sof.Options(tile=16, window=8, capacity=1000, order_slots=100).c_struct()
     hp = ctypes.cast(cam, ctypes.c_void_p)
-    assert L.sof_workspace_size(100, hp, 1, ctypes.byref(o), ctypes.byref(p), ctypes.byref(b), ctypes.byref(g)) == 0
+    assert L.sof_workspace_size(100, hp, 1, ctypes.byref(o), ctypes.byref(p), ctypes.byref(b), ctypes.byref(g),
+                                ctypes.byref(r)) == 0
     assert p.value > 0 and b.value > 0 and g.value == 1000 * 64
+    # recorded order: a 256-byte aligned flag per tile (12 tiles of 16 x 16), then 2 bytes per
+    # slot and tile-padded pixel
+    assert r.value == 256 + 12 * 256 * 100 * 2
+    none = sof.Options(tile=16, window=8, capacity=1000, order_slots=0).c_struct()
+    assert L.sof_workspace_size(100, hp, 1, ctypes.byref(none), None, None, None, ctypes.byref(r)) == 0
+    assert r.value == 0
+    for slots in (-1, 4097):
+        bad = sof.Options(tile=16, window=8, capacity=1000, order_slots=slots).c_struct()
+        assert L.sof_workspace_size(100, hp, 1, ctypes.byref(bad), None, None, None, None) == sof.SOF_E_ARG
     bad = sof.Options(tile=12, window=8, capacity=1000).c_struct()
-    assert L.sof_workspace_size(100, hp, 1, ctypes.byref(bad), None, None, None) == sof.SOF_E_ARG
+    assert L.sof_workspace_size(100, hp, 1, ctypes.byref(bad), None, None, None, None) == sof.SOF_E_ARG
     bad = sof.Options(tile=16, window=5, capacity=1000).c_struct()
-    assert L.sof_workspace_size(100, hp, 1, ctypes.byref(bad), None, None, None) == sof.SOF_E_UNSUPPORTED
-    assert L.sof_workspace_size(-1, hp, 1, ctypes.byref(o), None, None, None) == sof.SOF_E_ARG
+    assert L.sof_workspace_size(100, hp, 1, ctypes.byref(bad), None, None, None, None) == sof.SOF_E_UNSUPPORTED
+    assert L.sof_workspace_size(-1, hp, 1, ctypes.byref(o), None, None, None, None) == sof.SOF_E_ARG
     cam[0].width = 0
-    assert L.sof_workspace_size(100, hp, 1, ctypes.byref(o), None, None, None) == sof.SOF_E_ARG
+    assert L.sof_workspace_size(100, hp, 1, ctypes.byref(o), None, None, None, None) == sof.SOF_E_ARG
     cam[0].width = 64
     # binary-search step: empty input is a no-op, missing arrays or a negative size are rejected
     assert L.sof_bisect_step(None, None, None, None, 0, None) == sof.SOF_OK
@@ -72,12 +82,23 @@ def test_host_argument_checks():
     big = ctypes.c_size_t(1 << 40)
     gs0 = sof.CGaussians(0, 0, 0, None, None, None, None, None)
 
-    def bwd(normal, grads, grad_bytes):
-        return L.sof_render_bwd(ctypes.byref(gs0), hp, fake, 1, ctypes.byref(o), None, 0, fake, big, fake, normal,
-                                fake, fake, None, None, fake, None, None, None, None, None, grads, grad_bytes,
-                                None, None, None, None, None, None)
+    def bwd(normal, grads, grad_bytes, order=None, order_bytes=0, opts=o):
+        return L.sof_render_bwd(ctypes.byref(gs0), hp, fake, 1, ctypes.byref(opts), None, 0, fake, big, fake, normal,
+                                fake, order, order_bytes, fake, None, None, fake, None, None, None, None, None, grads,
+                                grad_bytes, None, None, None, None, None, None)
     assert bwd(None, fake, big) == sof.SOF_E_ARG
     assert bwd(fake, fake, 0) == sof.SOF_E_WORKSPACE
+    # a recorded order: smaller than its size, or given with order_slots = 0, is rejected
+    L.sof_workspace_size(100, hp, 1, ctypes.byref(o), None, None, None, ctypes.byref(r))
+    assert bwd(fake, fake, big, order=fake, order_bytes=r.value - 1) == sof.SOF_E_WORKSPACE
+    assert bwd(fake, fake, big, order=fake, order_bytes=big, opts=none) == sof.SOF_E_ARG
+    # the forward: the same checks, and a recorded order needs aux
+    def fwd(order, order_bytes, aux, opts=o):
+        return L.sof_render_fwd(0, hp, hp, 1, ctypes.byref(opts), None, 0, fake, big, None, None, None, None, aux,
+                                None, order, order_bytes, None)
+    assert fwd(fake, r.value - 1, fake) == sof.SOF_E_WORKSPACE
+    assert fwd(fake, big, fake, opts=none) == sof.SOF_E_ARG
+    assert fwd(fake, big, None) == sof.SOF_E_ARG
 
 
 def test_render_order_argument_checks():
@@ -108,8 +129,8 @@ def test_static_backward_rejects_capacity_above_its_scratch():
     """sof_render_bwd_static refuses a capacity above its fixed scratch before any device call."""
     L = sof.lib()
     o = sof.Options(tile=16, window=8, capacity=sof.STATIC_SCRATCH_INSTANCES + 1).c_struct()
-    args = [None] * 27
-    args[3], args[6], args[8] = 1, 0, 0                  # n_cams, proj_bytes, bins_bytes
+    args = [None] * 29
+    args[3], args[6], args[8], args[13] = 1, 0, 0, 0     # n_cams, proj_bytes, bins_bytes, order_bytes
     plain = list(args)
     args[4] = ctypes.byref(o)
     assert L.sof_render_bwd_static(*args) == sof.SOF_E_SCRATCH

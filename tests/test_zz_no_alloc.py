@@ -33,7 +33,7 @@ def _static(r, g, C, out, ups):
                quats=torch.full_like(g.quats, float("nan")), opac=torch.full_like(g.opac, float("nan")),
                sh=torch.full_like(g.sh, float("nan")))
     sof.render_bwd_static(g, C, r.opts, r.proj, r.bins, out["rgb"], out["normal"], out["aux"], *ups, res["means"],
-                          res["scales"], res["quats"], res["opac"], res["sh"])
+                          res["scales"], res["quats"], res["opac"], res["sh"], order=out["order"])
     return res
 
 
