@@ -15,8 +15,9 @@
  *                      (Eq. (1)) of colour, normal and opacity, and the exact 0.5-level-set
  *                      depth (Sec. 3.2 "Exact Depth", App. A.3).
  *   sof_render_opacity opacity field at each pixel's rendered depth (Sec. 3.3, the L_opa term).
- *   sof_render_bwd     adjoint of render + project: replays each pixel's order front to back,
- *                      recomputing transmittance, and writes gradients for mu, s, q, o, f.
+ *   sof_render_bwd     adjoint of render + project: walks each pixel's order front to back
+ *                      (recorded by the forward, or replayed), recomputing transmittance, and
+ *                      writes gradients for mu, s, q, o, f.
  *   sof_filter3d       the 3D filter's opacity and covariance adjustment (App. "Dead Gaussians").
  *   sof_opacity_query  opacity field O(x) = min over views of O_N(x) (Eq. (12)-(13)) at
  *                      arbitrary points, with tile scheduling of points (Sec. 3.4, Eq. (14))
@@ -239,17 +240,18 @@ int sof_render_order(int64_t n, const sof_camera* h_cams, const sof_camera* d_ca
  * x = o + t_r d, t_r the depth the forward wrote, over the Gaussians the pixel blended, each
  * with alpha = min(0.99, o_i G_i(min(t*_i, t_r))) and counted when alpha >= 1/255 and the
  * evaluated point lies beyond the near plane (Eq. (12)); 0 where there is no crossing.
- * The pass replays the forward's per-pixel order.  With `losses` (the forward's [6,H,W]
- * losses output, or NULL) it uses the paper's split O_N = O_k + T_k sum_{i >= k} alpha_i
- * prod_{k <= j < i} (1 - alpha_j): the forward accumulated the part from the crossing
- * Gaussian k on, and the replay stops in front of k; with NULL it replays every blended
- * Gaussian.  Both give O_N up to float rounding.  Overwrites opacity [sum of W H].  The
- * L_opa loss |O_N - 0.5|^2 is the caller's to form.
+ * The pass walks the forward's per-pixel order: read from `order` (NULL, or the forward's
+ * recorded order with the same opts->order_slots; the tiles it flagged are replayed) or
+ * replayed.  With `losses` (the forward's [6,H,W] losses output, or NULL) it uses the paper's
+ * split O_N = O_k + T_k sum_{i >= k} alpha_i prod_{k <= j < i} (1 - alpha_j): the forward
+ * accumulated the part from the crossing Gaussian k on, and the walk stops in front of k; with
+ * NULL it walks every blended Gaussian.  All give O_N up to float rounding.  Overwrites
+ * opacity [sum of W H].  The L_opa loss |O_N - 0.5|^2 is the caller's to form.
  */
 int sof_render_opacity(int64_t n, const sof_camera* h_cams, const sof_camera* d_cams, int32_t n_cams,
                        const sof_options* opts, const void* proj, size_t proj_bytes, const void* bins,
                        size_t bins_bytes, const float* depth, const float* aux, const float* losses,
-                       float* opacity, hipStream_t stream);
+                       const void* order, size_t order_bytes, float* opacity, hipStream_t stream);
 
 /*
  * sof_render_bwd -- adjoint of sof_render_fwd, sof_render_opacity and sof_project.

@@ -275,12 +275,13 @@ int sof_filter3d_bwd(const sof_gaussians* g, const float* var, const float* d_sc
 
 int sof_render_opacity(int64_t n, const sof_camera* h_cams, const sof_camera* d_cams, int32_t n_cams,
                        const sof_options* opts, const void* proj, size_t proj_bytes, const void* bins,
-                       size_t bins_bytes, const float* depth, const float* aux, const float* losses, float* opacity,
-                       hipStream_t stream) {
+                       size_t bins_bytes, const float* depth, const float* aux, const float* losses,
+                       const void* order, size_t order_bytes, float* opacity, hipStream_t stream) {
   RenderOpaArgs a;
   int64_t n_tiles = 0;
   int st = fill_fwd_args(n, h_cams, d_cams, n_cams, opts, proj, proj_bytes, bins, bins_bytes, &a.f, &n_tiles);
   if (st) return st;
+  if ((st = set_order(opts, n_tiles, order, order_bytes, &a.f))) return st;
   if (!depth || !aux || !opacity) return SOF_E_ARG;
   a.f.depth = (float*)depth;
   a.f.aux = (float*)aux;
@@ -341,7 +342,7 @@ static int render_bwd_impl(const sof_gaussians* g, const sof_camera* h_cams, con
   pa.offsets = (const int64_t*)(bb + B.offsets);
   pa.count_total = (const int64_t*)(bb + B.status);
   pa.cap = opts->capacity;
-  pa.grads = (const float*)grads;
+  pa.grads = (float*)grads;
   pa.d_means = d_means; pa.d_scales = d_scales; pa.d_quats = d_quats; pa.d_opac = d_opacities; pa.d_sh = d_sh;
   return hip_status(launch_project_bwd(pa, stream));
 }

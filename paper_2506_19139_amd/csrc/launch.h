@@ -113,7 +113,7 @@ struct ProjectBwdArgs {
   const int64_t* offsets;
   const int64_t* count_total;
   int64_t cap;
-  const float* grads;
+  float* grads;             // per-instance partials; reduced in place per (camera, Gaussian)
   float* d_means;
   float* d_scales;
   float* d_quats;

@@ -1,9 +1,12 @@
 // Reduction of per-instance gradient partials and the chain rule back to the Gaussian
-// parameters (adjoint of sof_project).  One thread per Gaussian: for every camera it sums
-// the partials of the Gaussian's instances (contiguous in emission order, summed in that fixed
-// order, so this sum adds no order dependence of its own), maps the camera-space (mu_c, P_c) gradients to
-// world space, adds the view-dependent colour and normal terms, and finally chains the
-// world precision P = R diag(1/s^2) R^T to scales and the quaternion.
+// parameters (adjoint of sof_project), in two kernels.  k_grad_reduce: one thread per
+// (camera, Gaussian) sums the partials of its instances (contiguous in emission order, summed
+// in that fixed order, so this sum adds no order dependence of its own) into the slot of its
+// first instance; a light kernel, so many waves keep these dependent loads in flight.
+// k_project_bwd: one thread per Gaussian reads those sums for every camera, maps the
+// camera-space (mu_c, P_c) gradients to world space, adds the view-dependent colour and normal
+// terms, and finally chains the world precision P = R diag(1/s^2) R^T to scales and the
+// quaternion.
 #include "launch.h"
 #include "sh_eval.h"
 
@@ -17,6 +20,35 @@ __device__ inline void store_rows(const float* lds, float* dst, int64_t row0, in
   const int total = rows * width;
   float* out = dst + row0 * width;
   for (int k = threadIdx.x; k < total; k += kPbThreads) out[k] = lds[k];
+}
+
+constexpr int kGrThreads = 256;
+
+__global__ __launch_bounds__(kGrThreads) void k_grad_reduce(const int32_t* counts, const int64_t* offsets,
+                                                           const int64_t* count_total, int64_t cap, int64_t vn,
+                                                           float* grads) {
+  const int64_t vg = (int64_t)blockIdx.x * kGrThreads + threadIdx.x;
+  if (vg >= vn) return;
+  const int cnt = counts[vg];
+  if (cnt <= 1) return;                                   // one instance is its own sum
+  const int64_t kinst = *count_total < cap ? *count_total : cap;
+  const int64_t e0 = offsets[vg];
+  const int64_t e1 = (e0 + cnt < kinst) ? e0 + cnt : kinst;
+  if (e0 >= e1) return;
+  float4 s[kGradFields / 4];
+#pragma unroll
+  for (int f4 = 0; f4 < kGradFields / 4; ++f4) s[f4] = make_float4(0.f, 0.f, 0.f, 0.f);
+  for (int64_t e = e0; e < e1; ++e) {
+    const float4* src = (const float4*)(grads + (size_t)e * kGradFields);
+#pragma unroll
+    for (int f4 = 0; f4 < kGradFields / 4; ++f4) {
+      const float4 v = src[f4];
+      s[f4].x += v.x; s[f4].y += v.y; s[f4].z += v.z; s[f4].w += v.w;
+    }
+  }
+  float4* dst = (float4*)(grads + (size_t)e0 * kGradFields);
+#pragma unroll
+  for (int f4 = 0; f4 < kGradFields / 4; ++f4) dst[f4] = s[f4];
 }
 
 template <int DEG>
@@ -56,17 +88,19 @@ __global__ __launch_bounds__(kPbThreads) void k_project_bwd(ProjectBwdArgs a) {
     const int cnt = a.counts[vg];
     if (cnt == 0) continue;
     touched = true;
+    // the sum over this camera's instances, left in the first one's slot by k_grad_reduce
+    // (none when the instances were dropped at the capacity)
     const int64_t e0 = a.offsets[vg];
-    const int64_t e1 = (e0 + cnt < kinst) ? e0 + cnt : kinst;
     float gsum[kGradFields];
 #pragma unroll
     for (int f4 = 0; f4 < kGradFields; ++f4) gsum[f4] = 0.f;
-    for (int64_t e = e0; e < e1; ++e) {
-      const float4* src = (const float4*)(a.grads + (size_t)e * kGradFields);
+    if (e0 < kinst) {
+      const float4* src = (const float4*)(a.grads + (size_t)e0 * kGradFields);
 #pragma unroll
       for (int f4 = 0; f4 < kGradFields / 4; ++f4) {
         const float4 v = src[f4];
-        gsum[4 * f4] += v.x; gsum[4 * f4 + 1] += v.y; gsum[4 * f4 + 2] += v.z; gsum[4 * f4 + 3] += v.w;
+        gsum[4 * f4] = 0.f + v.x; gsum[4 * f4 + 1] = 0.f + v.y; gsum[4 * f4 + 2] = 0.f + v.z;
+        gsum[4 * f4 + 3] = 0.f + v.w;
       }
     }
     const sof_camera cam = a.cams[c];
@@ -174,6 +208,11 @@ __global__ __launch_bounds__(kPbThreads) void k_project_bwd(ProjectBwdArgs a) {
 
 hipError_t launch_project_bwd(const ProjectBwdArgs& a, hipStream_t s) {
   if (a.n <= 0) return hipSuccess;
+  const int64_t vn = a.n * a.n_cams;
+  hipLaunchKernelGGL(k_grad_reduce, dim3((unsigned)div_up(vn, kGrThreads)), dim3(kGrThreads), 0, s, a.counts,
+                     a.offsets, a.count_total, a.cap, vn, a.grads);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
   const int th = kPbThreads;
   const dim3 grid((unsigned)div_up(a.n, th)), block(th);
   switch (a.sh_degree) {

@@ -74,7 +74,7 @@ _SIGS = {
     "sof_render_order": (ctypes.c_int, [ctypes.c_int64, _P, _P, ctypes.c_int32, _P, _P, ctypes.c_size_t, _P,
                                         ctypes.c_size_t, _P, ctypes.c_int64, ctypes.c_int32, _P, _P, _P, _P, _P]),
     "sof_render_opacity": (ctypes.c_int, [ctypes.c_int64, _P, _P, ctypes.c_int32, _P, _P, ctypes.c_size_t, _P,
-                                          ctypes.c_size_t, _P, _P, _P, _P, _P]),
+                                          ctypes.c_size_t, _P, _P, _P, _P, ctypes.c_size_t, _P, _P]),
     "sof_render_bwd": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, _P, _P, ctypes.c_size_t, _P, ctypes.c_size_t,
                                       _P, _P, _P, _P, ctypes.c_size_t, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
                                       ctypes.c_size_t, _P, _P, _P, _P, _P, _P]),
@@ -266,11 +266,11 @@ def render_order(n, cams: Cameras, opts: Options, proj, bins, slot, n_slots, max
     return stream_ids[:n_slots], stream_keys[:n_slots], emit_ids[:n_slots], counts[:n_slots]
 
 
-def render_opacity(n, cams: Cameras, opts: Options, proj, bins, depth, aux, opacity, losses=None):
+def render_opacity(n, cams: Cameras, opts: Options, proj, bins, depth, aux, opacity, losses=None, order=None):
     o = opts.c_struct()
     _check(lib().sof_render_opacity(n, cams.hp(), cams.dp(), len(cams), ctypes.byref(o), _ptr(proj), proj.numel(),
-                                    _ptr(bins), bins.numel(), _ptr(depth), _ptr(aux), _ptr(losses), _ptr(opacity),
-                                    _stream()), "sof_render_opacity")
+                                    _ptr(bins), bins.numel(), _ptr(depth), _ptr(aux), _ptr(losses), _ptr(order),
+                                    _nbytes(order), _ptr(opacity), _stream()), "sof_render_opacity")
 
 
 def render_bwd(g: Gaussians, cams: Cameras, opts: Options, proj, bins, rgb, normal, aux, d_rgb, d_acc, d_depth,
@@ -564,7 +564,7 @@ class Rasterizer:
             out["opa"] = torch.empty(self.cams.n_pixels, device=self.device)
         losses = out.get("losses") if split else None
         render_opacity(g.n, self.cams, self.opts, self.proj, self.bins, out["depth"], out["aux"], out["opa"],
-                       losses=losses)
+                       losses=losses, order=out.get("order"))
         return out["opa"]
 
     def backward(self, g: Gaussians, out, d_rgb=None, d_acc=None, d_depth=None, d_normal=None, grads_out=None,

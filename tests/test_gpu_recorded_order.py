@@ -152,3 +152,19 @@ def test_a_tile_list_longer_than_two_to_the_sixteen_is_replayed():
     assert longest > 65536 and n_emit.max() <= opts.order_slots
     assert flags.all()
     _same(*_backward_both(r, g, out, _upstream(C, 6)))
+
+
+@pytest.mark.parametrize("split", [True, False])
+def test_opacity_pass_from_the_recorded_order_equals_the_replay(split):
+    """The opacity at the rendered depth (Sec. 3.3) walking the recorded order against the
+    replaying pass, with and without the paper's split, also with tiles flagged for replay."""
+    scene, cam = scenes.small_scene(), scenes.small_camera()
+    for slots in (sof.DEFAULT_ORDER_SLOTS, 12):
+        print(f"[case] opacity pass, recorded vs replayed, split {split}, {slots} slots", flush=True)
+        r, g, C, opts, out = _render(scene, cam, 16, 8, order_slots=slots, losses=True)
+        rec = r.opacity(g, out, split=split).clone()
+        rep = r.opacity(g, {**out, "order": None}, split=split).clone()
+        torch.cuda.synchronize()
+        a, b = rec.cpu().numpy(), rep.cpu().numpy()
+        assert np.abs(a - b).max() <= 1e-6, np.abs(a - b).max()
+        assert (b > 0).sum() > 100

@@ -74,7 +74,7 @@ def test_host_argument_checks():
     assert L.sof_filter3d(ctypes.byref(gs), None, None, 0, 0.0, 0.2, None, None, None, None) == sof.SOF_E_ARG
     assert L.sof_filter3d_bwd(ctypes.byref(gs), None, None, None, None, None, None) == sof.SOF_OK
     # opacity pass: the forward's depth and aux are required
-    assert L.sof_render_opacity(0, hp, hp, 1, ctypes.byref(o), None, 0, None, 0, None, None, None, None,
+    assert L.sof_render_opacity(0, hp, hp, 1, ctypes.byref(o), None, 0, None, 0, None, None, None, None, 0, None,
                                 None) == sof.SOF_E_ARG
     # backward: a normal gradient needs the forward's normal (checked before any launch; with
     # the normal given, the next check reached is the too-small partials buffer)
