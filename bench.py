@@ -675,6 +675,12 @@ def main():
     if peaks:
         roofline["measured_peaks"] = peaks
         roofline["frac_of_measured_fma"] = round(achieved / peaks["fma_TFLOPs"], 4)
+    # the two rasteriser kernels together (the recorded order moves the per-pixel order's work
+    # from the backward to the forward, so the pair is the fairer unit of the step)
+    pair_ms = kern["render_fwd"] + kern["render_bwd"]
+    pair_tflops = (fwd_flops + bwd_flops) / (pair_ms * 1e-3) / 1e12
+    roofline["rasteriser_pair"] = {"flop": int(fwd_flops + bwd_flops), "kernel_ms": round(pair_ms, 4),
+                                   "achieved": round(pair_tflops, 3), "frac": round(pair_tflops / FP32_PEAK_TFLOPS, 4)}
     # every kernel of the step and the query with counter figures taken on its current sources
     per_kernel = {k: {"us": float(r["avg_us"]), "bytes": int(float(r["read_bytes"]) + float(r["write_bytes"])),
                       "hbm_frac": float(r["hbm_frac"]), "issue_frac": float(r["issue_frac"]),
