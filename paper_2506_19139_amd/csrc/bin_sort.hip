@@ -341,28 +341,42 @@ __global__ __launch_bounds__(256) void k_emit(const short4* rect, const float4* 
   // the loop and the shuffles run on all 64 lanes (total is wave-uniform); only the stores
   // are predicated
   const int excl = incl - cnt;
-  for (int j0 = 0; j0 < total; j0 += 64) {
-    const int j = j0 + lane;
-    // owner: the first lane whose inclusive prefix exceeds j (it has a non-zero count)
-    int lo = 0, hi = 63;
+  // kEmitUnroll instances per lane and step: their tile-counter atomics are all in flight
+  // before the first returned rank is stored
+  constexpr int kEmitUnroll = 4;
+  for (int j0 = 0; j0 < total; j0 += 64 * kEmitUnroll) {
+    uint32_t rk[kEmitUnroll];
+    int64_t ee[kEmitUnroll];
+    bool ok[kEmitUnroll];
 #pragma unroll
-    for (int it = 0; it < 6; ++it) {
-      const int mid = (lo + hi) >> 1;
-      const bool right = __shfl(incl, mid, 64) <= j;
-      lo = right ? mid + 1 : lo;
-      hi = right ? hi : mid;
+    for (int u = 0; u < kEmitUnroll; ++u) {
+      const int j = j0 + 64 * u + lane;
+      // owner: the first lane whose inclusive prefix exceeds j (it has a non-zero count)
+      int lo = 0, hi = 63;
+#pragma unroll
+      for (int it = 0; it < 6; ++it) {
+        const int mid = (lo + hi) >> 1;
+        const bool right = __shfl(incl, mid, 64) <= j;
+        lo = right ? mid + 1 : lo;
+        hi = right ? hi : mid;
+      }
+      const int before = __shfl(excl, lo, 64);
+      ee[u] = e0 + j;
+      ok[u] = j < total && ee[u] < cap;
+      rk[u] = 0u;
+      if (ok[u]) {
+        const EmitOwner o = own[w][lo];
+        const int local = j - before;
+        const int ty = o.ty0 + local / o.nx, tx = o.tx0 + local % o.nx;
+        const uint32_t t = (uint32_t)(o.toff + ty * o.tiles_x + tx);
+        rk[u] = (uint32_t)atomicAdd(&ranges[t].y, 1);
+        inst[ee[u]] = make_uint2(t, o.key);
+        gid[ee[u]] = o.g;
+      }
     }
-    const int before = __shfl(excl, lo, 64);
-    const int64_t e = e0 + j;
-    if (j < total && e < cap) {
-      const EmitOwner o = own[w][lo];
-      const int local = j - before;
-      const int ty = o.ty0 + local / o.nx, tx = o.tx0 + local % o.nx;
-      const uint32_t t = (uint32_t)(o.toff + ty * o.tiles_x + tx);
-      rank[e] = (uint32_t)atomicAdd(&ranges[t].y, 1);
-      inst[e] = make_uint2(t, o.key);
-      gid[e] = o.g;
-    }
+#pragma unroll
+    for (int u = 0; u < kEmitUnroll; ++u)
+      if (ok[u]) rank[ee[u]] = rk[u];
   }
 }
 
