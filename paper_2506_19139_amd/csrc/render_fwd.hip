@@ -68,10 +68,9 @@ __device__ inline float blend(PixFwd& p, float alpha, uint32_t gid, const float4
 // known, and from k on every blended Gaussian's alpha at x = o + t_r d (t_eval = min(t*,
 // t_r), the 1/255 and near-plane rules of Eq. (12)) multiplies Pt = prod_{i >= k} (1 -
 // alpha_i(x)); the second pass then needs only the Gaussians in front of k.
-__device__ inline void loss_terms(PixFwd& p, float w, float sstar, uint32_t gid, const float4* geom, int64_t cam_base,
-                                  int px, int py, float dn, bool crossed_here, uint32_t flags, float near_plane) {
-  const int64_t vg = cam_base + gid;
-  const float4 r0 = geom[4 * vg], r1 = geom[4 * vg + 1], r2 = geom[4 * vg + 2], r3 = geom[4 * vg + 3];
+__device__ inline void loss_terms(PixFwd& p, float w, float sstar, const float4& r0, const float4& r1, const float4& r2,
+                                  const float4& r3, int px, int py, float dn, bool crossed_here, uint32_t flags,
+                                  float near_plane) {
   const float2 d2 = pixel_offset(r0, px, py);
   const Quad q = quad_terms(r1.x, r1.y, r1.z, r1.w, r2.x, r2.y, r2.z, r2.w, d2.x, d2.y);
   // hardware reciprocals (1 ulp): these values only enter the losses, never a decision
@@ -183,6 +182,7 @@ __global__ __launch_bounds__(TS * TS, (MODE != kFwdPlain || TS < 16) ? 1 : (W <=
   __shared__ uint2 srect[B];
   __shared__ int32_t gring[NR];
   __shared__ float4 aring[2 * NR];               // colour, normal
+  __shared__ float4 lring[LOSS ? 4 * NR : 1];    // geometry record (the loss terms read it)
   const int tile = blockIdx.x;
   const int c = find_cam(a.cam_info, a.n_cams, tile);
   const CamInfo ci = a.cam_info[c];
@@ -286,7 +286,15 @@ __global__ __launch_bounds__(TS * TS, (MODE != kFwdPlain || TS < 16) ? 1 : (W <=
         recw[n_before * 64 + (int)(threadIdx.x & 63)] = (uint16_t)et;
     }
     if constexpr (LOSS) {
-      if (w > 0.f) loss_terms(p, w, ek, g, a.geom, cam_base, px, py, dn, k_before < 0 && p.k >= 0, a.flags, near_plane);
+      if (w > 0.f) {
+        const int r = (int)(et % NR);
+        float4 r0 = lring[4 * r], r1 = lring[4 * r + 1], r2 = lring[4 * r + 2], r3 = lring[4 * r + 3];
+        if ((int)et < (cur_b - 1) * B) {                 // older than the ring
+          const int64_t vg = cam_base + g;
+          r0 = a.geom[4 * vg]; r1 = a.geom[4 * vg + 1]; r2 = a.geom[4 * vg + 2]; r3 = a.geom[4 * vg + 3];
+        }
+        loss_terms(p, w, ek, r0, r1, r2, r3, px, py, dn, k_before < 0 && p.k >= 0, a.flags, near_plane);
+      }
     }
   };
 
@@ -303,6 +311,11 @@ __global__ __launch_bounds__(TS * TS, (MODE != kFwdPlain || TS < 16) ? 1 : (W <=
         gring[r] = g;
         aring[2 * r] = a.app[2 * (cam_base + g)];
         aring[2 * r + 1] = a.app[2 * (cam_base + g) + 1];
+        if constexpr (LOSS) {
+          const int64_t vg = cam_base + g;
+#pragma unroll
+          for (int k = 0; k < 4; ++k) lring[4 * r + k] = a.geom[4 * vg + k];
+        }
       }
     }
     __syncthreads();
