@@ -458,105 +458,167 @@ __global__ __launch_bounds__(256) void k_tile_scatter(const uint2* inst, const u
   bucket[ranges[it.x].x + rank[e]] = ((uint64_t)it.y << 32) | (uint64_t)e;
 }
 
-// Bitonic sort of P (a power of two, <= kTileSortCap) keys in LDS by the whole workgroup,
-// with the network unrolled at compile time (no scalar loop or branch work per stage).  Lane
-// t takes the compare-exchange pairs t, t + 256, ...; pair p of a stage with distance j joins
-// entries i = 2 j (p / j) + p mod j and i + j.  For j < 64 both entries lie in one 64-entry
-// block whose 32 pairs belong to 32 consecutive lanes of one wave, so those stages need only
-// the wave's own ordering of its LDS accesses; a workgroup barrier is taken only around
-// stages whose pairs span waves (j >= 64).
-constexpr int kTileSortThreads = 256, kTileSortCap = 2048;
+// Per-tile sort: one wave per tile, the keys in registers.  A list of L <= kTileSortCap entries
+// is padded to P = 64 E entries (E a power of two, the smallest with P >= L; the padding holds
+// the largest key) and lane l holds entries i = l E + k, k < E.  A bitonic network then sorts
+// them: a compare-exchange of entries i and i ^ J (ascending where i & K is clear, K the size
+// of the merged block) joins two registers of one lane when J < E, else the same register of
+// lanes l and l ^ (J / E), whose values a DPP move (lane distance 1, 2, 4, 8) or a row or
+// half-wave swap (16, 32) brings over.  No LDS and no barrier: at the benchmark's sizes
+// (lists of about 400 entries, E = 8) 24 of the 45 stages stay inside a lane and 18 of the
+// others use DPP.
+constexpr int kTileSortThreads = 64, kTileSortCap = 2048;
 
-__device__ inline void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+constexpr int kDppQuadXor1 = 0xB1;       // quad permutation (1, 0, 3, 2): lane i ^ 1
+constexpr int kDppQuadXor2 = 0x4E;       // quad permutation (2, 3, 0, 1): lane i ^ 2
+constexpr int kDppQuadRev = 0x1B;        // quad permutation (3, 2, 1, 0): lane i ^ 3
+constexpr int kDppRowHalfMirror = 0x141; // lane i of a half-row reads lane 7 - i: i ^ 7
+constexpr int kDppRowRor8 = 0x128;       // rotate a row of 16 lanes by 8: i ^ 8
+
+template <int CTRL>
+__device__ inline uint32_t dpp_u32(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xF, 0xF, true);
 }
 
-template <int P, int K, int J>
-__device__ inline void bitonic_stage(uint64_t* s) {
-  constexpr int kPairs = P / 2;
-#pragma unroll
-  for (int p0 = 0; p0 < kPairs; p0 += kTileSortThreads) {
-    const int p = p0 + (int)threadIdx.x;
-    if (kPairs % kTileSortThreads == 0 || p < kPairs) {
-      const int i = ((p & ~(J - 1)) << 1) | (p & (J - 1));
-      const int l = i | J;
-      const uint64_t a = s[i], b = s[l];
-      const bool sw = (a > b) == ((i & K) == 0);
-      s[i] = sw ? b : a;
-      s[l] = sw ? a : b;
-    }
-  }
-  constexpr bool next_crosses = (J > 1) ? ((J >> 1) >= 64) : (2 * K <= P && K >= 64);
-  if constexpr (J >= 64 || next_crosses) {
-    __syncthreads();
+// The value of lane l ^ D (D a power of two below 64).
+template <int D>
+__device__ inline uint32_t lane_xor_u32(uint32_t v, bool lower) {
+  if constexpr (D == 1) return dpp_u32<kDppQuadXor1>(v);
+  else if constexpr (D == 2) return dpp_u32<kDppQuadXor2>(v);
+  else if constexpr (D == 4) return dpp_u32<kDppQuadRev>(dpp_u32<kDppRowHalfMirror>(v));   // (i ^ 7) ^ 3
+  else if constexpr (D == 8) return dpp_u32<kDppRowRor8>(v);
+  else if constexpr (D == 16) {
+    // odd rows of the first operand swap with even rows of the second: with both the same,
+    // the first result holds rows (0, 0, 2, 2) and the second rows (1, 1, 3, 3)
+    const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+    return lower ? r[1] : r[0];
   } else {
-    wave_lds_sync();
+    // upper half of the first operand swaps with the lower half of the second
+    const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    return lower ? r[1] : r[0];
   }
 }
 
-template <int P, int K, int J>
-__device__ inline void bitonic_merge(uint64_t* s) {
-  bitonic_stage<P, K, J>(s);
-  if constexpr (J > 1) bitonic_merge<P, K, J / 2>(s);
+template <int D>
+__device__ inline uint64_t lane_xor_u64(uint64_t v, bool lower) {
+  const uint32_t lo = lane_xor_u32<D>((uint32_t)v, lower);
+  const uint32_t hi = lane_xor_u32<D>((uint32_t)(v >> 32), lower);
+  return ((uint64_t)hi << 32) | lo;
 }
 
-template <int P, int K = 2>
-__device__ inline void bitonic_sort(uint64_t* s) {
-  bitonic_merge<P, K, K / 2>(s);
-  if constexpr (K < P) bitonic_sort<P, 2 * K>(s);
+// Compare-exchange of two entries of one lane (the smaller to x when up).
+__device__ inline void ce_pair(uint64_t& x, uint64_t& y, bool up) {
+  const uint64_t a = x, b = y;
+  const bool sw = (a > b) == up;
+  x = sw ? b : a;
+  y = sw ? a : b;
 }
 
-// Sort s[0, P) for the smallest power of two P >= L (entries L..P-1 hold the largest key).
-__device__ __attribute__((always_inline)) inline void lds_bitonic(uint64_t* s, int P) {
-  switch (P) {
-    case 2: bitonic_sort<2>(s); break;
-    case 4: bitonic_sort<4>(s); break;
-    case 8: bitonic_sort<8>(s); break;
-    case 16: bitonic_sort<16>(s); break;
-    case 32: bitonic_sort<32>(s); break;
-    case 64: bitonic_sort<64>(s); break;
-    case 128: bitonic_sort<128>(s); break;
-    case 256: bitonic_sort<256>(s); break;
-    case 512: bitonic_sort<512>(s); break;
-    case 1024: bitonic_sort<1024>(s); break;
-    default: bitonic_sort<kTileSortCap>(s); break;
+// Blocks of K <= E entries lie inside one lane: the first phases of the network.
+template <int E, int K = 2>
+__device__ inline void wave_bitonic_in_lane(uint64_t (&v)[E], int lane) {
+  if constexpr (K <= E) {
+#pragma unroll
+    for (int J = K / 2; J >= 1; J >>= 1)
+#pragma unroll
+      for (int k = 0; k < E; ++k)
+        if ((k & J) == 0) ce_pair(v[k], v[k | J], (((lane * E) + k) & K) == 0);
+    wave_bitonic_in_lane<E, 2 * K>(v, lane);
   }
-  __syncthreads();
 }
 
-// One workgroup per tile: its range sorted by (depth key, emission index); the emission
-// indices are written to vals.  Ranges above kTileSortCap (not met at the benchmark's
-// sizes, where the longest list is about a thousand) are sorted in chunks of kTileSortCap
-// in LDS and then merged pairwise in global memory, each element placed by its rank in the
-// other run (keys are unique), ping-ponging between bucket and tmp.
-__global__ __launch_bounds__(kTileSortThreads) void k_tile_sort(const int2* ranges, uint64_t* bucket, uint64_t* tmp,
+// Stage J = D E of a phase K > J: lane l keeps the smaller of its entry and lane l ^ D's
+// when keep_min.
+template <int E, int D>
+__device__ inline void wave_bitonic_lanes(uint64_t (&v)[E], bool lower, bool keep_min) {
+#pragma unroll
+  for (int k = 0; k < E; ++k) {
+    const uint64_t o = lane_xor_u64<D>(v[k], lower);
+    v[k] = ((o < v[k]) == keep_min) ? o : v[k];
+  }
+}
+
+// Phases K = 2 E .. 64 E run as a loop (the stages between lanes picked by their distance),
+// so that the code of one E stays small; each phase ends with its stages inside the lane,
+// whose direction is the lane's for the whole phase.
+template <int E>
+__device__ inline void wave_bitonic_sort(uint64_t (&v)[E], int lane) {
+  wave_bitonic_in_lane<E>(v, lane);
+  for (int K = 2 * E; K <= 64 * E; K <<= 1) {
+    const bool up = ((lane * E) & K) == 0;
+    for (int D = K / (2 * E); D >= 1; D >>= 1) {
+      const bool lower = (lane & D) == 0;
+      const bool keep_min = up == lower;
+      switch (D) {
+        case 1: wave_bitonic_lanes<E, 1>(v, lower, keep_min); break;
+        case 2: wave_bitonic_lanes<E, 2>(v, lower, keep_min); break;
+        case 4: wave_bitonic_lanes<E, 4>(v, lower, keep_min); break;
+        case 8: wave_bitonic_lanes<E, 8>(v, lower, keep_min); break;
+        case 16: wave_bitonic_lanes<E, 16>(v, lower, keep_min); break;
+        default: wave_bitonic_lanes<E, 32>(v, lower, keep_min); break;
+      }
+    }
+#pragma unroll
+    for (int J = E / 2; J >= 1; J >>= 1)
+#pragma unroll
+      for (int k = 0; k < E; ++k)
+        if ((k & J) == 0) ce_pair(v[k], v[k | J], up);
+  }
+}
+
+// Sort src[0, m) (m <= 64 E) by the wave; the sorted keys go to dst, or their low words
+// (emission indices) to vals when dst is null.
+template <int E>
+__device__ __attribute__((always_inline)) inline void wave_sort_chunk(const uint64_t* src, int m, uint64_t* dst,
+                                                                      uint32_t* vals) {
+  const int lane = (int)(threadIdx.x & 63);
+  uint64_t v[E];
+#pragma unroll
+  for (int k = 0; k < E; ++k) {
+    const int i = lane * E + k;
+    v[k] = i < m ? src[i] : ~0ull;
+  }
+  wave_bitonic_sort<E>(v, lane);
+  if (dst) {
+#pragma unroll
+    for (int k = 0; k < E; ++k)
+      if (lane * E + k < m) dst[lane * E + k] = v[k];
+  } else {
+#pragma unroll
+    for (int k = 0; k < E; ++k)
+      if (lane * E + k < m) vals[lane * E + k] = (uint32_t)v[k];
+  }
+}
+
+__device__ __attribute__((always_inline)) inline void wave_sort_any(const uint64_t* src, int m, uint64_t* dst,
+                                                                    uint32_t* vals) {
+  if (m <= 64) wave_sort_chunk<1>(src, m, dst, vals);
+  else if (m <= 128) wave_sort_chunk<2>(src, m, dst, vals);
+  else if (m <= 256) wave_sort_chunk<4>(src, m, dst, vals);
+  else if (m <= 512) wave_sort_chunk<8>(src, m, dst, vals);
+  else if (m <= 1024) wave_sort_chunk<16>(src, m, dst, vals);
+  else wave_sort_chunk<32>(src, m, dst, vals);
+}
+
+// One wave per tile: its range sorted by (depth key, emission index); the emission indices are
+// written to vals.  Ranges above kTileSortCap (not met at the benchmark's sizes, where the
+// longest list is about a thousand) are sorted in chunks of kTileSortCap and then merged
+// pairwise in global memory, each element placed by its rank in the other run (keys are
+// unique), ping-ponging between bucket and tmp.
+// Four waves per SIMD (128 VGPRs): 0.224 against 0.239 ms for the whole bin sort without a
+// bound (208 VGPRs); only the 2048-entry variant, for lists above 1024, spills.
+__global__ __launch_bounds__(kTileSortThreads, 4) void k_tile_sort(const int2* ranges, uint64_t* bucket, uint64_t* tmp,
                                                                 uint32_t* vals) {
-  __shared__ uint64_t s[kTileSortCap];
   const int2 rg = ranges[blockIdx.x];
   const int L = rg.y - rg.x;
   if (L <= 0) return;
-  const bool small = L <= kTileSortCap;
-  int P = 2;
-  while (P < L && P < kTileSortCap) P <<= 1;
   uint64_t* src = bucket + rg.x;
   uint64_t* dst = tmp + rg.x;
-  // one LDS sort per chunk of kTileSortCap entries (a single chunk for a short list, whose
-  // sorted emission indices go straight to vals)
-  for (int c0 = 0; c0 < L; c0 += kTileSortCap) {
-    const int m = min(kTileSortCap, L - c0);
-    for (int i = threadIdx.x; i < P; i += kTileSortThreads) s[i] = i < m ? src[c0 + i] : ~0ull;
-    __syncthreads();
-    lds_bitonic(s, P);
-    if (small) {
-      for (int i = threadIdx.x; i < m; i += kTileSortThreads) vals[rg.x + i] = (uint32_t)s[i];
-    } else {
-      for (int i = threadIdx.x; i < m; i += kTileSortThreads) src[c0 + i] = s[i];
-    }
-    __syncthreads();
-  }
+  const bool small = L <= kTileSortCap;
+  for (int c0 = 0; c0 < L; c0 += kTileSortCap)
+    wave_sort_any(src + c0, min(kTileSortCap, L - c0), small ? nullptr : src + c0, vals + rg.x);
   if (small) return;
+  __syncthreads();
   for (int width = kTileSortCap; width < L; width <<= 1) {
     for (int i = threadIdx.x; i < L; i += kTileSortThreads) {
       const int lo = (i / (2 * width)) * (2 * width);

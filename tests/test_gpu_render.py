@@ -83,8 +83,8 @@ def test_tile_lists_bit_exact():
 
 def _dense_scene(n=5000, seed=7):
     """Large, overlapping Gaussians in front of the small camera: most of them touch every
-    tile, so the tile lists run to thousands of entries (above the 2048 that one workgroup
-    sorts in LDS at once)."""
+    tile, so the tile lists run to thousands of entries (above the 2048 that one wave sorts
+    in registers at once)."""
     rng = np.random.default_rng(seed)
     means = np.concatenate([rng.uniform(-0.6, 0.6, (n, 2)), rng.uniform(-1.0, 1.0, (n, 1))], 1)
     return dict(means=means.astype(np.float32), scales=np.exp(rng.normal(-1.0, 0.2, (n, 3))).astype(np.float32),
@@ -103,7 +103,7 @@ def test_long_tile_lists_bit_exact(tile):
     ids_o, tiles_o, ranges_o = O.tile_lists(pv["rect"].astype(np.int64), pv["mu_z"], tile, cam["width"], cam["height"])
     longest = int(np.max(ranges_o[:, 1] - ranges_o[:, 0]))
     print(f"  longest tile list {longest}")
-    assert longest > 4096                       # chunked LDS sorts and two or more merge passes
+    assert longest > 4096                       # chunked register sorts and two or more merge passes
     _same_ranges(ranges, ranges_o)
     assert np.array_equal(ids.astype(np.int64), ids_o)
 
