@@ -1,8 +1,8 @@
 // Reduction of per-instance gradient partials and the chain rule back to the Gaussian
-// parameters (adjoint of sof_project), in two kernels.  k_grad_reduce: one thread per
+// parameters (adjoint of sof_project), in two kernels.  k_grad_reduce: the lane of each
 // (camera, Gaussian) sums the partials of its instances (contiguous in emission order, summed
 // in that fixed order, so this sum adds no order dependence of its own) into the slot of its
-// first instance; a light kernel, so many waves keep these dependent loads in flight.
+// first instance, its wave streaming the partials through LDS.
 // k_project_bwd: one thread per Gaussian reads those sums for every camera, maps the
 // camera-space (mu_c, P_c) gradients to world space, adds the view-dependent colour and normal
 // terms, and finally chains the world precision P = R diag(1/s^2) R^T to scales and the
@@ -23,47 +23,95 @@ __device__ inline void store_rows(const float* lds, float* dst, int64_t row0, in
 }
 
 constexpr int kGrThreads = 256;
+constexpr int kGrWindow = 64;                   // instances per LDS window of a wave
+constexpr int kGrRow = kGradFields + 4;         // LDS row stride (16-B aligned; rows start in
+                                                // different banks)
+constexpr int kGrLoads = kGrWindow * kGradFields / 4 / 64;   // float4 loads per lane and window
+typedef float f32x4 __attribute__((ext_vector_type(4)));       // kept in registers (an array of
+                                                               // HIP's float4 went to scratch)
 
+// The partials of instances [w0, min(w0 + kGrWindow, Eend)) of a wave's run, one float4 per
+// lane and load; every load unconditional (the index clamped into the window), so that they
+// are in flight together (predicated loads were each waited for on their own).
+__device__ __attribute__((always_inline)) inline void gr_load_window(const float* grads, int64_t w0, int64_t Eend,
+                                                                     int lane, f32x4 (&buf)[kGrLoads]) {
+  const int nf = (int)((Eend - w0 < kGrWindow ? Eend - w0 : kGrWindow) * (kGradFields / 4));
+  const f32x4* src = (const f32x4*)(grads + (size_t)w0 * kGradFields);
+#pragma unroll
+  for (int r = 0; r < kGrLoads; ++r) {
+    const int f = lane + 64 * r;
+    buf[r] = src[f < nf ? f : nf - 1];
+  }
+}
+
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// A wave owns 64 consecutive (camera, Gaussian) pairs, whose instances are one contiguous run
+// of partials.  The run streams through an LDS window of kGrWindow instances with coalesced
+// loads (the next window's loads in flight while the current one is summed), and each lane
+// adds its own instances from LDS in emission order, so the sum is the one a lane reading its
+// instances one by one would form.  (Each lane loading its own instances from global memory
+// took 145 us at 1M Gaussians 1080p: the loop runs as long as the wave's largest count, with
+// a dependent global round trip per step.)
 __global__ __launch_bounds__(kGrThreads) void k_grad_reduce(const int32_t* counts, const int64_t* offsets,
                                                            const int64_t* count_total, int64_t cap, int64_t vn,
                                                            float* grads) {
-  const int64_t vg = (int64_t)blockIdx.x * kGrThreads + threadIdx.x;
-  if (vg >= vn) return;
-  const int cnt = counts[vg];
-  if (cnt <= 1) return;                                   // one instance is its own sum
+  __shared__ __align__(16) float win[kGrThreads / 64][kGrWindow * kGrRow];
+  const int lane = (int)(threadIdx.x & 63), w = (int)(threadIdx.x >> 6);
+  const int64_t base = ((int64_t)blockIdx.x * (kGrThreads / 64) + w) * 64;
+  if (base >= vn) return;                                 // wave-uniform
+  const int64_t vg = base + lane;
   const int64_t kinst = *count_total < cap ? *count_total : cap;
-  const int64_t e0 = offsets[vg];
+  const int cnt = vg < vn ? counts[vg] : 0;
+  const int64_t e0 = vg < vn ? offsets[vg] : 0;
   const int64_t e1 = (e0 + cnt < kinst) ? e0 + cnt : kinst;
-  if (e0 >= e1) return;
+  const bool need = e1 - e0 >= 2;                         // one instance is its own sum
+  if (__ballot(need) == 0) return;
+  int total = cnt;
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) total += __shfl_xor(total, d, 64);
+  const int64_t E0 = offsets[base];
+  const int64_t Eend = (E0 + total < kinst) ? E0 + total : kinst;
+  float* lw = win[w];
   float4 s[kGradFields / 4];
 #pragma unroll
   for (int f4 = 0; f4 < kGradFields / 4; ++f4) s[f4] = make_float4(0.f, 0.f, 0.f, 0.f);
-  // four instances per step: their loads are all in flight before the first add (most
-  // Gaussians have four instances or fewer); the adds keep the emission order.  (Streaming a
-  // wave's contiguous run of partials through LDS measured slower: 162 against 145 us at 1M
-  // Gaussians 1080p, the 24 KB buffer leaving one or two waves per SIMD.)
-  constexpr int kChunk = 4;
-  for (int64_t e = e0; e < e1; e += kChunk) {
-    float4 v[kChunk][kGradFields / 4];
+  f32x4 buf[kGrLoads];
+  gr_load_window(grads, E0, Eend, lane, buf);
+  for (int64_t w0 = E0; w0 < Eend; w0 += kGrWindow) {
 #pragma unroll
-    for (int j = 0; j < kChunk; ++j) {
-      const float4* src = (const float4*)(grads + (size_t)(e + j < e1 ? e + j : e0) * kGradFields);
-#pragma unroll
-      for (int f4 = 0; f4 < kGradFields / 4; ++f4) v[j][f4] = src[f4];
+    for (int r = 0; r < kGrLoads; ++r) {
+      const int f = lane + 64 * r;
+      *(f32x4*)&lw[(f >> 2) * kGrRow + (f & 3) * 4] = buf[r];
     }
-#pragma unroll
-    for (int j = 0; j < kChunk; ++j) {
-      if (e + j < e1) {
+    wave_lds_sync();
+    // the next window's loads (the last window re-reads itself: no branch around the loads,
+    // which would keep buf out of registers)
+    gr_load_window(grads, w0 + kGrWindow < Eend ? w0 + kGrWindow : w0, Eend, lane, buf);
+    if (need) {
+      const int a = (int)((e0 > w0 ? e0 : w0) - w0);
+      const int b = (int)((e1 < w0 + kGrWindow ? e1 : w0 + kGrWindow) - w0);
+#pragma unroll 2
+      for (int k = a; k < b; ++k) {
+        const float4* row = (const float4*)&lw[k * kGrRow];
 #pragma unroll
         for (int f4 = 0; f4 < kGradFields / 4; ++f4) {
-          s[f4].x += v[j][f4].x; s[f4].y += v[j][f4].y; s[f4].z += v[j][f4].z; s[f4].w += v[j][f4].w;
+          const float4 v = row[f4];
+          s[f4].x += v.x; s[f4].y += v.y; s[f4].z += v.z; s[f4].w += v.w;
         }
       }
     }
+    wave_lds_sync();
   }
-  float4* dst = (float4*)(grads + (size_t)e0 * kGradFields);
+  if (need) {
+    float4* dst = (float4*)(grads + (size_t)e0 * kGradFields);
 #pragma unroll
-  for (int f4 = 0; f4 < kGradFields / 4; ++f4) dst[f4] = s[f4];
+    for (int f4 = 0; f4 < kGradFields / 4; ++f4) dst[f4] = s[f4];
+  }
 }
 
 template <int DEG>
