@@ -7,16 +7,16 @@
 // Render lists (and the query's lists when tile ids need more than 20 bits) are built by
 // bucketing, not by a global sort: each instance takes its rank inside its tile with an
 // atomic increment of the tile's counter, one workgroup scans the counters into the tile
-// ranges, instances are scattered into their tile's range, and one workgroup per tile sorts
-// its range in LDS by (depth key, emission index).  Emission indices grow with the Gaussian
+// ranges, instances are scattered into their tile's range, and one wave per tile sorts its
+// range in registers by (depth key, emission index).  Emission indices grow with the Gaussian
 // index inside a camera, and a tile holds one camera's instances, so this is the order
 // (tile, depth key, Gaussian index) whatever order the atomics handed out.
 //
-// Radix sort: 8-bit digits, 2048 keys per workgroup of 256 lanes (4 wave64s).  Per pass a
-// histogram kernel writes per-(digit, block) counts digit-major, an exclusive scan turns
-// them into global offsets, and a scatter kernel ranks keys stably inside the workgroup:
-// each wave owns 512 consecutive keys, walks them in input order, groups equal digits with
-// 8 ballots and keeps running per-digit counts in LDS.
+// Radix sort: 8-bit digits, 4096 32-bit keys (2048 64-bit keys) per workgroup of 256 lanes
+// (4 wave64s).  Per pass a histogram kernel writes per-(digit, block) counts digit-major, an
+// exclusive scan turns them into global offsets, and a scatter kernel ranks keys stably
+// inside the workgroup: each wave owns a run of consecutive keys, walks them in input order,
+// groups equal digits with 8 ballots and keeps running per-digit counts in LDS.
 #include "launch.h"
 
 namespace sof {

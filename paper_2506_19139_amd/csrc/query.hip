@@ -81,12 +81,11 @@ __global__ __launch_bounds__(256) void k_pv_count(const float* pts, int64_t np, 
   cnt[p] = c;
 }
 
-__device__ inline uint32_t quantised_depth(double z, float near_plane, int bits) {
-  // log-spaced over [near, near * 2^20]; only used to order points inside a tile
-  const double l = log2(z / (double)near_plane) * (1.0 / 20.0);
-  const double m = (double)((1u << bits) - 1u);
-  const double q = l <= 0.0 ? 0.0 : (l >= 1.0 ? m : l * m);
-  return (uint32_t)q;
+// Depth part of a pair key: the lists' depth key of the point's view depth (float bits, so no
+// logarithm), cut to the bits left beside the tile id.  It only orders the points of a tile
+// (the evaluation recomputes each point's own key), so any monotone map would do.
+__device__ inline uint32_t pair_depth_bits(double z, int bits) {
+  return bits > 0 ? query_depth_key((float)z, query_key_shift(bits)) : 0u;
 }
 
 // The pairs of a wave's 64 points fill one contiguous range (the scan's offset of its first
@@ -117,7 +116,7 @@ __global__ __launch_bounds__(256) void k_pv_emit(const float* pts, int64_t np, c
       const int64_t e = base + run + __popcll(m & below);
       if (e < pvcap) {
         const uint32_t t = (uint32_t)(ci[v].tile_off + ((int)w / tile) * ci[v].tiles_x + ((int)u / tile));
-        keys[e] = (t << dbits) | quantised_depth(zc, near_plane, dbits);
+        keys[e] = (t << dbits) | pair_depth_bits(zc, dbits);
         vals[e] = (uint32_t)p;
       } else {
         over = true;
