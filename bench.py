@@ -40,11 +40,14 @@ FLOP_ADJ = 110      # one blended Gaussian in the backward: dalpha, chain to (mu
 
 
 # Counter figures (HBM bytes, vector and LDS instructions) are taken with rocprofv3 over this
-# benchmark and written by `bench.py --summarize` into the profile summary below, one line per
-# kernel with the hash of the sources the kernel is built from.  The bench line reports a
-# kernel's counter figures only while its sources still hash to that value and the workload is
-# the default one; a changed source needs a new measurement.
-PROFILE = os.path.join(ROOT, "profiles", "step_1M_1080p_and_query_3M_27M_counters.txt")
+# benchmark and written by `bench.py --summarize` into the profile summaries below (the training
+# step alone, then the query workload), one line per kernel with the hash of the sources the
+# kernel is built from.  The bench line reports a kernel's counter figures only while its
+# sources still hash to that value and the workload is the default one; a changed source needs
+# a new measurement.  A kernel in both summaries takes the step's line (its launches there are
+# all of the step's size).
+PROFILES = [os.path.join(ROOT, "profiles", "query_3M_27M_counters.txt"),
+            os.path.join(ROOT, "profiles", "step_1M_1080p_counters.txt")]
 CSRC = os.path.join(ROOT, "paper_2506_19139_amd", "csrc")
 VALU_CYCLES = 4                     # a wave64 vector instruction holds a 16-lane SIMD for 4 cycles
 N_SIMDS, CLOCK_GHZ = 1024, 2.4      # 256 CUs x 4 SIMDs
@@ -82,16 +85,18 @@ def kernel_source_hash(short):
     return h.hexdigest()[:16]
 
 
-def read_profile(path=PROFILE):
-    """Per-kernel records of a profile summary (lines `kernel=... src=... key=value ...`)."""
+def read_profile(path=None):
+    """Per-kernel records of a profile summary (lines `kernel=... src=... key=value ...`); with
+    no path, of the default summaries (a later file's line replaces an earlier one's)."""
     rec = {}
-    if not os.path.exists(path):
-        return rec
-    for line in open(path):
-        if not line.startswith("kernel="):
+    for pth in ([path] if path else PROFILES):
+        if not os.path.exists(pth):
             continue
-        fields = dict(tok.split("=", 1) for tok in line.strip().split("\t"))
-        rec[fields["kernel"]] = fields
+        for line in open(pth):
+            if not line.startswith("kernel="):
+                continue
+            fields = dict(tok.split("=", 1) for tok in line.strip().split("\t"))
+            rec[fields["kernel"]] = fields
     return rec
 
 
@@ -705,7 +710,7 @@ def main():
                    "instances": int(k_used), "blended_per_pixel": round(n_emit / P, 2)},
         "per_call_ms": {k: round(v, 4) for k, v in per.items()},
         "roofline": roofline,
-        "per_kernel": {"source": os.path.relpath(PROFILE, ROOT), "kernels": per_kernel},
+        "per_kernel": {"source": [os.path.relpath(p, ROOT) for p in PROFILES], "kernels": per_kernel},
     }
 
     if not args.no_graph_step:
