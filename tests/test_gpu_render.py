@@ -108,6 +108,56 @@ def test_long_tile_lists_bit_exact(tile):
     assert np.array_equal(ids.astype(np.int64), ids_o)
 
 
+# list lengths around every register size class of the per-tile sort (64 E entries, E = 1 ..
+# 32), the chunked sort with global merges above 2048, and empty tiles
+_CLASS_LENGTHS = [0, 1, 2, 7, 33, 63, 64, 65, 100, 127, 128, 129, 200, 255, 256, 257, 300, 511, 512, 513,
+                  700, 1023, 1024, 1025, 1500, 2047, 2048, 2049, 2500, 3000, 0, 5000]
+
+
+def _one_tile_scene(lengths, cam, tile, seed=11):
+    """Tiny Gaussians, each inside a single pixel of its tile, lengths[k] of them in tile k;
+    half take their depth from three exact values, so keys tie and the emission index
+    decides."""
+    rng = np.random.default_rng(seed)
+    tx = cam["width"] // tile
+    means = []
+    for k, n in enumerate(lengths):
+        x0, y0 = (k % tx) * tile, (k // tx) * tile
+        j = np.arange(n)
+        u = x0 + 2 + (j % (tile - 4)) + 0.5
+        v = y0 + 2 + (j // (tile - 4)) % (tile - 4) + 0.5
+        d = np.where(rng.uniform(size=n) < 0.5, rng.choice([2.5, 3.0, 3.5], n), rng.uniform(2.0, 6.0, n))
+        X = (u - float(cam["cx"])) * d / float(cam["fx"])
+        Y = (v - float(cam["cy"])) * d / float(cam["fy"])
+        means.append(np.stack([X, Y, d - 4.0], 1))          # small_camera: R = I, t = (0, 0, 4)
+    means = np.concatenate(means)
+    n = len(means)
+    perm = rng.permutation(n)                                # tiles' Gaussians interleaved in memory
+    means = means[perm]
+    return dict(means=means.astype(np.float32), scales=np.full((n, 3), 1e-4, np.float32),
+                quats=np.tile(np.array([1, 0, 0, 0], np.float32), (n, 1)), opac=np.full(n, 0.5, np.float32),
+                sh=rng.normal(0, 0.3, (n, 1, 3)).astype(np.float32), sh_degree=0)
+
+
+def test_tile_lists_every_sort_size_class():
+    tile = 16
+    cam = scenes.small_camera(width=128, height=64)
+    assert len(_CLASS_LENGTHS) == (cam["width"] // tile) * (cam["height"] // tile)
+    scene = _one_tile_scene(_CLASS_LENGTHS, cam, tile)
+    print(f"[case] per-tile sort size classes, {len(scene['opac'])} single-tile Gaussians 128x64 tile 16", flush=True)
+    r, g, C, opts, out, host = gpu_render(scene, [cam], tile=tile, window=8)
+    pv = sof.proj_view(r.proj, g.n, 1)
+    keys, ids, ranges = sof.sorted_instances(r.bins, g.n, C, opts)
+    ids_o, tiles_o, ranges_o = O.tile_lists(pv["rect"].astype(np.int64), pv["mu_z"], tile, cam["width"], cam["height"])
+    assert list(ranges_o[:, 1] - ranges_o[:, 0]) == _CLASS_LENGTHS      # the construction hit its tiles
+    _same_ranges(ranges, ranges_o)
+    assert np.array_equal(ids.astype(np.int64), ids_o)
+    # ties resolved by the emission (Gaussian) index inside every tile
+    k = pv["mu_z"][ids_o]
+    same = (k[1:] == k[:-1]) & (tiles_o[1:] == tiles_o[:-1])
+    assert same.sum() > 1000 and np.all(ids_o[1:][same] > ids_o[:-1][same])
+
+
 def test_tile_size_invariance_bitwise():
     scene, cam = _small()
     res = []
