@@ -289,7 +289,7 @@ __global__ __launch_bounds__(256) void k_count(const short4* rect, int64_t vn, i
 
 // One instance per (camera, Gaussian, touched tile), in emission order e (the scan of the
 // per-Gaussian counts): its tile, depth key and Gaussian, and its rank inside the tile from
-// an atomic increment of the tile's counter (ranges[t].y, zeroed by k_bin_init).  Instances
+// an atomic increment of the tile's counter (ranges[t].y, zeroed by k_bin_count).  Instances
 // with e >= cap are dropped and flagged.  Each wave owns 64 consecutive (camera, Gaussian)
 // pairs and hands out their instances one per lane (an owner search over the wave's
 // inclusive prefix of counts), so a wave's 64 atomics and stores issue together and the
@@ -380,30 +380,57 @@ __global__ __launch_bounds__(256) void k_emit(const short4* rect, const float4* 
   }
 }
 
-// Camera table, status reset and zeroed tile counters.
-__global__ __launch_bounds__(256) void k_bin_init(const sof_camera* cams, int n_cams, int tile, CamInfo* out,
-                                                  StatusBlock* status, int2* ranges, int64_t n_tiles) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n_tiles) ranges[i] = make_int2(0, 0);
-  if (i != 0) return;
-  int32_t toff = 0;
-  int64_t poff = 0;
-  for (int c = 0; c < n_cams; ++c) {
-    CamInfo ci;
-    ci.tiles_x = (cams[c].width + tile - 1) / tile;
-    ci.tiles_y = (cams[c].height + tile - 1) / tile;
-    ci.tile_off = toff;
-    ci.pix_off = poff;
-    ci.pad = 0; ci.pad2 = 0;
-    out[c] = ci;
-    toff += ci.tiles_x * ci.tiles_y;
-    poff += (int64_t)cams[c].width * cams[c].height;
+// The first dispatch of the render lists: camera table and status reset (thread 0), zeroed
+// tile counters, each (camera, Gaussian)'s count of touched tiles, and the per-chunk sums of
+// those counts (the first step of the exclusive scan that gives the emission offsets).
+// One dispatch instead of three: each of these light kernels cost 4-6 us at 1M Gaussians.
+__device__ inline int32_t rect_tile_count(short4 r, int tile) {
+  return (r.x <= r.z && r.y <= r.w) ? (r.z / tile - r.x / tile + 1) * (r.w / tile - r.y / tile + 1) : 0;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_bin_count(const sof_camera* cams, int n_cams, int tile,
+                                                            CamInfo* out, StatusBlock* status, int2* ranges,
+                                                            int64_t n_tiles, const short4* rect, int64_t vn,
+                                                            int32_t* counts, int64_t* sums) {
+  __shared__ int64_t lw[4];
+  const int64_t gid = (int64_t)blockIdx.x * kScanThreads + threadIdx.x;
+  for (int64_t t = gid; t < n_tiles; t += (int64_t)gridDim.x * kScanThreads) ranges[t] = make_int2(0, 0);
+  if (gid == 0) {
+    int32_t toff = 0;
+    int64_t poff = 0;
+    for (int c = 0; c < n_cams; ++c) {
+      CamInfo ci;
+      ci.tiles_x = (cams[c].width + tile - 1) / tile;
+      ci.tiles_y = (cams[c].height + tile - 1) / tile;
+      ci.tile_off = toff;
+      ci.pix_off = poff;
+      ci.pad = 0; ci.pad2 = 0;
+      out[c] = ci;
+      toff += ci.tiles_x * ci.tiles_y;
+      poff += (int64_t)cams[c].width * cams[c].height;
+    }
+    CamInfo end;
+    end.tile_off = toff; end.pix_off = poff; end.tiles_x = end.tiles_y = 0; end.pad = 0; end.pad2 = 0;
+    out[n_cams] = end;
+    status->count = 0;
+    status->flags = 0;
   }
-  CamInfo end;
-  end.tile_off = toff; end.pix_off = poff; end.tiles_x = end.tiles_y = 0; end.pad = 0; end.pad2 = 0;
-  out[n_cams] = end;
-  status->count = 0;
-  status->flags = 0;
+  // only the chunk's total is needed here, so the lanes read consecutive records (the
+  // offsets kernel then gives each thread its own run of kScanItems)
+  const int64_t base = (int64_t)blockIdx.x * kScanChunk + threadIdx.x;
+  int64_t sum = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const int64_t i = base + (int64_t)k * kScanThreads;
+    if (i < vn) {
+      const int32_t c = rect_tile_count(rect[i], tile);
+      counts[i] = c;
+      sum += c;
+    }
+  }
+  int64_t total;
+  block_exclusive_scan<int64_t, int64_t>(sum, lw, total);
+  if (threadIdx.x == 0) sums[blockIdx.x] = total;
 }
 
 // Tile counters -> ranges [start, start + count) in one workgroup (an exclusive scan over
@@ -752,14 +779,14 @@ hipError_t launch_bin_sort(int64_t n, const sof_camera* d_cams, int n_cams, int6
   const float* zmin = (const float*)(pb + P.zmin);
 
   const int th = 256;
-  hipLaunchKernelGGL(k_bin_init, dim3((unsigned)div_up(n_tiles > 0 ? n_tiles : 1, th)), dim3(th), 0, s, d_cams, n_cams,
-                     tile, cams, status, ranges, n_tiles);
+  // init, counts and chunk sums; the chunk scan (writes the instance total); the offsets
+  const int64_t nch = div_up(vn > 0 ? vn : 1, kScanChunk);
+  hipLaunchKernelGGL(k_bin_count, dim3((unsigned)nch), dim3(kScanThreads), 0, s, d_cams, n_cams, tile, cams, status,
+                     ranges, n_tiles, rect, vn, counts, scan_tmp);
+  hipLaunchKernelGGL((k_scan_chunks<int64_t>), dim3(1), dim3(kScanThreads), 0, s, scan_tmp, nch, &status->count);
   if (vn > 0) {
-    hipLaunchKernelGGL(k_count, dim3((unsigned)div_up(vn, th)), dim3(th), 0, s, rect, vn, tile, counts);
-  }
-  hipError_t e = exclusive_scan<int32_t, int64_t>(counts, vn, offsets, scan_tmp, &status->count, s);
-  if (e != hipSuccess) return e;
-  if (vn > 0) {
+    hipLaunchKernelGGL((k_scan_apply<int32_t, int64_t>), dim3((unsigned)nch), dim3(kScanThreads), 0, s, counts, vn,
+                       scan_tmp, offsets);
     hipLaunchKernelGGL(k_emit, dim3((unsigned)div_up(vn, 256)), dim3(256), 0, s, rect, geom, zmin, n, vn, tile, cams,
                        counts, offsets, cap, query_keys, inst, rank, gid, ranges, status);
   }
