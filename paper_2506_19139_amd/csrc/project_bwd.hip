@@ -1,8 +1,8 @@
 // Reduction of per-instance gradient partials and the chain rule back to the Gaussian
 // parameters (adjoint of sof_project), in two kernels.  k_grad_reduce: the lane of each
-// (camera, Gaussian) sums the partials of its instances (contiguous in emission order, summed
-// in that fixed order, so this sum adds no order dependence of its own) into the slot of its
-// first instance, its wave streaming the partials through LDS.
+// (camera, Gaussian) gets the sum of the partials of its instances (contiguous in emission
+// order; added in a fixed order, so this sum adds no order dependence of its own) in the slot
+// of its first instance, its wave streaming the partials through LDS.
 // k_project_bwd: one thread per Gaussian reads those sums for every camera, maps the
 // camera-space (mu_c, P_c) gradients to world space, adds the view-dependent colour and normal
 // terms, and finally chains the world precision P = R diag(1/s^2) R^T to scales and the
@@ -52,15 +52,21 @@ __device__ inline void wave_lds_sync() {
 
 // A wave owns 64 consecutive (camera, Gaussian) pairs, whose instances are one contiguous run
 // of partials.  The run streams through an LDS window of kGrWindow instances with coalesced
-// loads (the next window's loads in flight while the current one is summed), and each lane
-// adds its own instances from LDS in emission order, so the sum is the one a lane reading its
-// instances one by one would form.  (Each lane loading its own instances from global memory
-// took 145 us at 1M Gaussians 1080p: the loop runs as long as the wave's largest count, with
-// a dependent global round trip per step.)
+// loads (the next window's loads in flight while the current one is summed).  Inside a window
+// the sums run across lanes, so that no lane waits for the Gaussian with the most instances:
+// lane r finds the owner of row r (a binary search over the wave's prefix of counts); lane
+// (f, q) adds field f over the 16 rows of quarter q, one run per owner, and leaves each run's
+// sum in the run's first row; the owner's lane then adds its (at most four) runs in order.
+// Every sum has a fixed order (rows in emission order inside a run, runs and windows in
+// order), so the result does not depend on scheduling.  (A lane adding its own rows one by
+// one took 67 us at 1M Gaussians 1080p, as long as the wave's largest count; each lane
+// loading its own instances from global memory 145 us.)
 __global__ __launch_bounds__(kGrThreads) void k_grad_reduce(const int32_t* counts, const int64_t* offsets,
                                                            const int64_t* count_total, int64_t cap, int64_t vn,
                                                            float* grads) {
   __shared__ __align__(16) float win[kGrThreads / 64][kGrWindow * kGrRow];
+  __shared__ __align__(16) int32_t own[kGrThreads / 64][kGrWindow];
+  static_assert(kGrWindow == 64 && kGradFields == 16, "one row per lane; 16 fields x 4 quarters of 16 rows");
   const int lane = (int)(threadIdx.x & 63), w = (int)(threadIdx.x >> 6);
   const int64_t base = ((int64_t)blockIdx.x * (kGrThreads / 64) + w) * 64;
   if (base >= vn) return;                                 // wave-uniform
@@ -71,12 +77,18 @@ __global__ __launch_bounds__(kGrThreads) void k_grad_reduce(const int32_t* count
   const int64_t e1 = (e0 + cnt < kinst) ? e0 + cnt : kinst;
   const bool need = e1 - e0 >= 2;                         // one instance is its own sum
   if (__ballot(need) == 0) return;
-  int total = cnt;
+  int incl = cnt;
 #pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) total += __shfl_xor(total, d, 64);
+  for (int d = 1; d < 64; d <<= 1) {
+    const int y = __shfl_up(incl, d, 64);
+    if (lane >= d) incl += y;
+  }
+  const int total = __shfl(incl, 63, 64);
   const int64_t E0 = offsets[base];
   const int64_t Eend = (E0 + total < kinst) ? E0 + total : kinst;
   float* lw = win[w];
+  int32_t* lo_own = own[w];
+  const int f = lane & 15, q = lane >> 4;                 // field and quarter of the run sums
   float4 s[kGradFields / 4];
 #pragma unroll
   for (int f4 = 0; f4 < kGradFields / 4; ++f4) s[f4] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -85,23 +97,62 @@ __global__ __launch_bounds__(kGrThreads) void k_grad_reduce(const int32_t* count
   for (int64_t w0 = E0; w0 < Eend; w0 += kGrWindow) {
 #pragma unroll
     for (int r = 0; r < kGrLoads; ++r) {
-      const int f = lane + 64 * r;
-      *(f32x4*)&lw[(f >> 2) * kGrRow + (f & 3) * 4] = buf[r];
+      const int fi = lane + 64 * r;
+      *(f32x4*)&lw[(fi >> 2) * kGrRow + (fi & 3) * 4] = buf[r];
+    }
+    {
+      // owner of row `lane`: the first lane whose inclusive prefix exceeds the row's offset
+      const int j = (int)(w0 - E0) + lane;
+      int lo = 0, hi = 63;
+#pragma unroll
+      for (int it = 0; it < 6; ++it) {
+        const int mid = (lo + hi) >> 1;
+        const bool right = __shfl(incl, mid, 64) <= j;
+        lo = right ? mid + 1 : lo;
+        hi = right ? hi : mid;
+      }
+      lo_own[lane] = (w0 + lane < Eend) ? lo : -1;
     }
     wave_lds_sync();
     // the next window's loads (the last window re-reads itself: no branch around the loads,
     // which would keep buf out of registers)
     gr_load_window(grads, w0 + kGrWindow < Eend ? w0 + kGrWindow : w0, Eend, lane, buf);
+    {
+      int ow[16];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int4 o4 = *(const int4*)&lo_own[16 * q + 4 * k];
+        ow[4 * k] = o4.x; ow[4 * k + 1] = o4.y; ow[4 * k + 2] = o4.z; ow[4 * k + 3] = o4.w;
+      }
+      float run = 0.f;
+      int cur = -1, start = 0;
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        const int r = 16 * q + k;
+        const float v = lw[r * kGrRow + f];
+        if (ow[k] != cur) {
+          if (cur >= 0) lw[start * kGrRow + f] = run;     // a row this lane has already read
+          cur = ow[k];
+          start = r;
+          run = 0.f;
+        }
+        run += v;
+      }
+      if (cur >= 0) lw[start * kGrRow + f] = run;
+    }
+    wave_lds_sync();
     if (need) {
       const int a = (int)((e0 > w0 ? e0 : w0) - w0);
       const int b = (int)((e1 < w0 + kGrWindow ? e1 : w0 + kGrWindow) - w0);
-#pragma unroll 2
-      for (int k = a; k < b; ++k) {
-        const float4* row = (const float4*)&lw[k * kGrRow];
+      if (a < b) {
+        for (int qq = a >> 4; qq <= (b - 1) >> 4; ++qq) {
+          const int r = a > 16 * qq ? a : 16 * qq;        // the first row of this lane's run in quarter qq
+          const float4* row = (const float4*)&lw[r * kGrRow];
 #pragma unroll
-        for (int f4 = 0; f4 < kGradFields / 4; ++f4) {
-          const float4 v = row[f4];
-          s[f4].x += v.x; s[f4].y += v.y; s[f4].z += v.z; s[f4].w += v.w;
+          for (int f4 = 0; f4 < kGradFields / 4; ++f4) {
+            const float4 v = row[f4];
+            s[f4].x += v.x; s[f4].y += v.y; s[f4].z += v.z; s[f4].w += v.w;
+          }
         }
       }
     }
