@@ -36,6 +36,10 @@ __device__ inline int clamp_floor(double v) {
   return (int)floor(v);
 }
 
+// Templated on the SH degree so that the coefficient loop is unrolled and its loads are all in
+// flight together (with a runtime degree each of its 16 iterations waited for its own load:
+// 82 us at 1M Gaussians 1080p).  DEG < 0: the query layout (no colour).
+template <int DEG>
 __global__ __launch_bounds__(256) void k_project(ProjectArgs a) {
   const int64_t vn = a.n * (int64_t)a.n_cams;
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -164,7 +168,7 @@ __global__ __launch_bounds__(256) void k_project(ProjectArgs a) {
   a.geom[4 * idx + 1] = r1;
   a.geom[4 * idx + 2] = r2;
   a.geom[4 * idx + 3] = r3;
-  if (a.query) return;
+  if (DEG < 0 || a.query) return;
   a.bwdr[2 * idx + 0] = make_float4((float)P[0], (float)P[1], (float)P[2], (float)P[3]);
   a.bwdr[2 * idx + 1] = make_float4((float)P[4], (float)P[5], (float)dmx, (float)dmy);
 
@@ -175,10 +179,12 @@ __global__ __launch_bounds__(256) void k_project(ProjectArgs a) {
   double ddx = mx - ccx, ddy = my - ccy, ddz = mz_w - ccz;
   const double dn = rsqrt(ddx * ddx + ddy * ddy + ddz * ddz);
   float Y[kMaxShCoeffs];
-  sh_basis(a.sh_degree, (float)(ddx * dn), (float)(ddy * dn), (float)(ddz * dn), Y);
-  const int K = (a.sh_degree + 1) * (a.sh_degree + 1);
+  constexpr int deg = DEG < 0 ? 0 : DEG;
+  sh_basis(deg, (float)(ddx * dn), (float)(ddy * dn), (float)(ddz * dn), Y);
+  constexpr int K = (deg + 1) * (deg + 1);
   const float* f = a.sh + (size_t)i * K * 3;
   float cr = 0.5f, cg = 0.5f, cb = 0.5f;
+#pragma unroll
   for (int k = 0; k < K; ++k) {
     cr = fmaf(Y[k], f[3 * k], cr);
     cg = fmaf(Y[k], f[3 * k + 1], cg);
@@ -227,7 +233,14 @@ hipError_t launch_project(const sof_gaussians* g, const sof_camera* d_cams, int 
   a.query = query ? 1 : 0;
   const int threads = 256;
   const int64_t blocks = div_up(vn, threads);
-  hipLaunchKernelGGL(k_project, dim3((unsigned)blocks), dim3(threads), 0, stream, a);
+  const dim3 grid((unsigned)blocks), block(threads);
+  if (query) hipLaunchKernelGGL(k_project<-1>, grid, block, 0, stream, a);
+  else switch (a.sh_degree) {
+    case 0: hipLaunchKernelGGL(k_project<0>, grid, block, 0, stream, a); break;
+    case 1: hipLaunchKernelGGL(k_project<1>, grid, block, 0, stream, a); break;
+    case 2: hipLaunchKernelGGL(k_project<2>, grid, block, 0, stream, a); break;
+    default: hipLaunchKernelGGL(k_project<3>, grid, block, 0, stream, a); break;
+  }
   if (query)
     hipLaunchKernelGGL(k_world, dim3((unsigned)div_up(g->n, threads)), dim3(threads), 0, stream, g->means, g->scales,
                        g->quats, g->n, a.world);
