@@ -128,6 +128,26 @@ constexpr int sort_items() { return sizeof(K) == 4 ? 2 * kSortItems : kSortItems
 template <typename K>
 constexpr int sort_tile() { return sort_items<K>() * kSortThreads; }
 
+// A thread's keys i0, i0 + 64, ... with every index clamped into [0, n) (zeros when n is 0), so
+// that the loads are unconditional and in flight together.
+template <typename K, typename T, int N>
+__device__ __attribute__((always_inline)) inline void load_clamped(const T* src, int64_t i0, int64_t n, T (&out)[N]) {
+  if (n > 0) {
+#pragma unroll
+    for (int it = 0; it < N; ++it) {
+      const int64_t i = i0 + it * 64;
+      out[it] = src[i < n ? i : n - 1];
+    }
+  } else {
+#pragma unroll
+    for (int it = 0; it < N; ++it) out[it] = T(0);
+  }
+}
+template <typename K, int N>
+__device__ __attribute__((always_inline)) inline void load_keys_clamped(const K* keys, int64_t i0, int64_t n, K (&out)[N]) {
+  load_clamped<K, K, N>(keys, i0, n, out);
+}
+
 template <typename K>
 __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const K* keys, const int64_t* count, int64_t cap,
                                                              int shift, int32_t* hist, int64_t nblocks) {
@@ -137,13 +157,13 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const K* keys, cons
   __syncthreads();
   const int64_t n = live_count(count, cap);
   const int64_t start = (int64_t)blockIdx.x * sort_tile<K>() + (int64_t)w * (sort_items<K>() * 64);
+  // all keys first (indices clamped into the live range), then the counts: a load inside
+  // each predicated step was waited for on its own
+  K kv[sort_items<K>()];
+  load_keys_clamped<K>(keys, start + lane, n, kv);
 #pragma unroll
   for (int it = 0; it < sort_items<K>(); ++it) {
-    const int64_t idx = start + it * 64 + lane;
-    if (idx < n) {
-      const int d = (int)((keys[idx] >> shift) & 0xFF);
-      atomicAdd(&cnt[w][d], 1);
-    }
+    if (start + it * 64 + lane < n) atomicAdd(&cnt[w][(int)((kv[it] >> shift) & 0xFF)], 1);
   }
   __syncthreads();
   const int t = threadIdx.x;
@@ -170,6 +190,8 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const K* keys_in
   uint32_t val[sort_items<K>()];
   int rank[sort_items<K>()];
   const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+  // (loading all keys and values first, as the histogram does, measured slower here: 8.0
+  // against 7.8 ms a pass at 1.1G keys; four waves per SIMD already hide these loads)
 #pragma unroll
   for (int it = 0; it < sort_items<K>(); ++it) {
     const int64_t idx = start + it * 64 + lane;
