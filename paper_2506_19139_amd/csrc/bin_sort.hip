@@ -47,14 +47,24 @@ __device__ inline Tacc block_exclusive_scan(Tacc v, Tacc* lds_wave, Tacc& total)
   return base + x - v;
 }
 
+// Both scan passes load all of a thread's items before using them, every index clamped into
+// [0, n) (n > 0 whenever they run): a load inside each predicated step was waited for on its
+// own.  The chunk sums need no particular assignment of items to lanes, so that pass reads
+// them coalesced.
 template <typename Tin, typename Tacc>
 __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const Tin* in, int64_t n, Tacc* sums) {
   __shared__ Tacc lw[4];
-  const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanItems;
+  const int64_t base = (int64_t)blockIdx.x * kScanChunk + threadIdx.x;
+  Tin raw[kScanItems];
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const int64_t i = base + (int64_t)k * kScanThreads;
+    raw[k] = in[i < n ? i : n - 1];
+  }
   Tacc s = 0;
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k)
-    if (base + k < n) s += (Tacc)in[base + k];
+    if (base + (int64_t)k * kScanThreads < n) s += (Tacc)raw[k];
   Tacc total;
   block_exclusive_scan<Tin, Tacc>(s, lw, total);
   if (threadIdx.x == 0) sums[blockIdx.x] = total;
@@ -80,11 +90,14 @@ template <typename Tin, typename Tout>
 __global__ __launch_bounds__(kScanThreads) void k_scan_apply(const Tin* in, int64_t n, const Tout* sums, Tout* out) {
   __shared__ Tout lw[4];
   const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanItems;
+  Tin raw[kScanItems];
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) raw[k] = in[base + k < n ? base + k : n - 1];
   Tout v[kScanItems];
   Tout s = 0;
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
-    v[k] = base + k < n ? (Tout)in[base + k] : 0;
+    v[k] = base + k < n ? (Tout)raw[k] : 0;
     s += v[k];
   }
   Tout total;
