@@ -453,12 +453,19 @@ __global__ __launch_bounds__(kScanThreads) void k_bin_count(const sof_camera* ca
   // only the chunk's total is needed here, so the lanes read consecutive records (the
   // offsets kernel then gives each thread its own run of kScanItems)
   const int64_t base = (int64_t)blockIdx.x * kScanChunk + threadIdx.x;
+  // all records first (indices clamped into [0, vn)), so the loads are in flight together
+  short4 rr[kScanItems];
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const int64_t i = base + (int64_t)k * kScanThreads;
+    rr[k] = vn > 0 ? rect[i < vn ? i : vn - 1] : make_short4(0, 0, -1, -1);
+  }
   int64_t sum = 0;
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
     const int64_t i = base + (int64_t)k * kScanThreads;
     if (i < vn) {
-      const int32_t c = rect_tile_count(rect[i], tile);
+      const int32_t c = rect_tile_count(rr[k], tile);
       counts[i] = c;
       sum += c;
     }
