@@ -96,3 +96,21 @@ def test_counter_figures_follow_workload_and_sources(tmp_path, monkeypatch):
     # changed kernel sources: no figure
     prof[k]["src"] = "0" * 16
     assert b.counter_figures(k, args, prof) is None
+
+
+def test_default_profiles_merge_with_the_step_summary_last(tmp_path, monkeypatch):
+    """A kernel in both default summaries takes the step summary's line (read last)."""
+    b = _bench()
+    k = "k_project<3>"
+
+    def line(us):
+        return "\t".join(f"{a}={v}" for a, v in dict(kernel=k, src=b.kernel_source_hash(k), avg_us=us, read_bytes="1",
+                                                     write_bytes="1", valu="1", hbm_frac="0.1", issue_frac="0.1",
+                                                     lds_bank_conflict="0").items())
+    query, step = tmp_path / "query.txt", tmp_path / "step.txt"
+    query.write_text("header\n" + line("7900") + "\n")
+    step.write_text("header\n" + line("57") + "\n")
+    monkeypatch.setattr(b, "PROFILES", [str(query), str(step)])
+    assert b.read_profile()[k]["avg_us"] == "57"
+    monkeypatch.setattr(b, "PROFILES", [str(query), str(tmp_path / "missing.txt")])
+    assert b.read_profile()[k]["avg_us"] == "7900"          # a missing summary is skipped
